@@ -1,0 +1,222 @@
+"""Seeded synthetic inputs for the slab hash: keys, values, queries, op batches, request streams.
+
+This module holds none of the hash table's own arithmetic (no bucket hash, no slab or allocator
+logic). It only draws random numbers, so the CPU oracle tests and the GPU path can share it.
+
+Randomness is SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number generators",
+OOPSLA 2014), used as a counter-based generator: output i (1-based) of a stream with seed s is
+mix(s + i * 0x9E3779B97F4A7C15 mod 2^64). The paper evaluates on uniformly random keys only
+(Performance Evaluation, bulk and concurrent benchmarks), so these inputs are the workload itself.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+#: The one reserved 32-bit key (the empty sentinel); never drawn as a key.
+RESERVED_KEY = 0xFFFFFFFF
+
+OP_SEARCH, OP_INSERT, OP_DELETE = 0, 1, 2
+
+
+def splitmix64_mix(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser on a uint64 array (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+class SplitMix64:
+    """Counter-based SplitMix64 stream; `next(n)` returns the next n uint64 outputs."""
+
+    def __init__(self, seed: int):
+        self.seed = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+        self.count = 0
+
+    def next(self, n: int) -> np.ndarray:
+        idx = np.arange(self.count + 1, self.count + 1 + n, dtype=np.uint64)
+        self.count += n
+        with np.errstate(over="ignore"):
+            return splitmix64_mix(self.seed + idx * GOLDEN)
+
+    def uniform(self, n: int) -> np.ndarray:
+        """n doubles in [0, 1) from the top 53 bits."""
+        return (self.next(n) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+    def below(self, n: int, bound: int) -> np.ndarray:
+        """n integers in [0, bound) by Lemire's multiply-shift on the high 32 bits (bound < 2^32)."""
+        assert 0 < bound <= 1 << 32
+        hi = (self.next(n) >> np.uint64(32)).astype(np.uint64)
+        with np.errstate(over="ignore"):
+            return ((hi * np.uint64(bound)) >> np.uint64(32)).astype(np.int64)
+
+    def permutation(self, n: int) -> np.ndarray:
+        """A uniformly random permutation of range(n) (sort by 64-bit random tags)."""
+        return np.argsort(self.next(n), kind="stable")
+
+
+def value_of(keys: np.ndarray) -> np.ndarray:
+    """Value stored with each key: low 32 bits of the SplitMix64 finaliser of the key."""
+    return (splitmix64_mix(np.asarray(keys, dtype=np.uint64)) & np.uint64(0xFFFFFFFF)).astype(
+        np.uint32)
+
+
+def unique_keys(rng: SplitMix64, n: int, exclude: np.ndarray | None = None) -> np.ndarray:
+    """n distinct uint32 keys in [0, 2^32-2] in stream order (high 32 bits of each output),
+    skipping the reserved key, repeats, and anything in `exclude`."""
+    out = np.empty(0, dtype=np.uint32)
+    excl = np.unique(np.asarray(exclude, dtype=np.uint32)) if exclude is not None else None
+    while out.size < n:
+        need = n - out.size
+        cand = (rng.next(need + need // 16 + 64) >> np.uint64(32)).astype(np.uint32)
+        cand = cand[cand != np.uint32(RESERVED_KEY)]
+        if excl is not None and excl.size:
+            cand = cand[~np.isin(cand, excl, assume_unique=False)]
+        allc = np.concatenate([out, cand])
+        _, first = np.unique(allc, return_index=True)
+        first.sort()
+        out = allc[first]
+    return out[:n].copy()
+
+
+def log_uniform_ints(rng: SplitMix64, n: int, lo: int, hi: int) -> np.ndarray:
+    """n integers, log-uniform on [lo, hi]: floor(exp(ln lo + U (ln(hi+1) - ln lo)))."""
+    u = rng.uniform(n)
+    v = np.floor(np.exp(math.log(lo) + u * (math.log(hi + 1) - math.log(lo)))).astype(np.int64)
+    return np.clip(v, lo, hi)
+
+
+def hash_params(rng: SplitMix64, prime: int) -> tuple[int, int]:
+    """The random multipliers of a universal hash modulo `prime`: a in [1, prime-1], b in
+    [0, prime-1]. The prime itself is a parameter of the table, not drawn here."""
+    r = rng.next(2)
+    a = 1 + int(r[0]) % (prime - 1)
+    b = int(r[1]) % prime
+    return a, b
+
+
+def zipf_ranks(rng: SplitMix64, n: int, num: int, s: float) -> np.ndarray:
+    """n ranks in [1, num] with P(r) proportional to r^-s (s > 1), by rejection-inversion
+    (Hormann & Derflinger, ACM TOMACS 1996)."""
+    assert s > 1.0 and num >= 1
+
+    def H(x):  # integral of (x)^-s
+        return (np.power(x, 1.0 - s) - 1.0) / (1.0 - s)
+
+    def Hinv(y):
+        return np.power(1.0 + y * (1.0 - s), 1.0 / (1.0 - s))
+
+    h_x1 = H(1.5) - 1.0
+    h_n = H(num + 0.5)
+    sconst = 2.0 - Hinv(H(2.5) - math.pow(2.0, -s))
+    out = np.empty(n, dtype=np.int64)
+    filled = 0
+    while filled < n:
+        m = (n - filled) * 2 + 64
+        u = h_n + rng.uniform(m) * (h_x1 - h_n)
+        x = Hinv(u)
+        k = np.clip(np.floor(x + 0.5), 1, num)
+        acc = (k - x <= sconst) | (u >= H(k + 0.5) - np.power(k, -s))
+        got = k[acc].astype(np.int64)
+        take = min(got.size, n - filled)
+        out[filled:filled + take] = got[:take]
+        filled += take
+    return out
+
+
+# --------------------------------------------------------------------------------------------
+# Workloads. Each returns plain numpy arrays; the table geometry (bucket count, pool size) is
+# chosen by the caller.
+
+@dataclass
+class Workload:
+    name: str
+    seed: int
+    hash_a: int = 0
+    hash_b: int = 0
+    arrays: dict = field(default_factory=dict)
+
+    def __getitem__(self, k):
+        return self.arrays[k]
+
+    def checksum(self) -> int:
+        h = np.uint64(self.seed)
+        for name in sorted(self.arrays):
+            a = np.ascontiguousarray(self.arrays[name]).view(np.uint8).astype(np.uint64)
+            with np.errstate(over="ignore"):
+                h = splitmix64_mix(np.array([h ^ np.uint64(int(a.sum()) & 0xFFFFFFFFFFFFFFFF)
+                                             ^ np.uint64(a.size)]))[0]
+        return int(h)
+
+
+def phased(seed: int, n: int, n_queries: int, hit_fraction: float, delete_fraction: float,
+           prime: int) -> Workload:
+    """Build n unique keys (value = value_of(key)); queries with the given hit fraction,
+    shuffled; and a random subset of the keys to delete."""
+    rng = SplitMix64(seed)
+    a, b = hash_params(rng, prime)
+    keys = unique_keys(rng, n)
+    vals = value_of(keys)
+    n_hit = int(round(n_queries * hit_fraction))
+    hit = keys[rng.permutation(n)[:n_hit]] if n_hit else np.empty(0, np.uint32)
+    miss = unique_keys(rng, n_queries - n_hit, exclude=keys)
+    q = np.concatenate([hit, miss])
+    q = q[rng.permutation(q.size)]
+    n_del = int(round(n * delete_fraction))
+    dels = keys[rng.permutation(n)[:n_del]]
+    return Workload("phased", seed, a, b, dict(keys=keys, vals=vals, queries=q, deletes=dels,
+                                               miss=miss, hit=hit))
+
+
+def bulk(seed: int, n: int, prime: int) -> Workload:
+    """n unique keys/values; an all-hit query set (a random permutation of the keys) and an
+    all-miss set (n fresh keys)."""
+    rng = SplitMix64(seed)
+    a, b = hash_params(rng, prime)
+    keys = unique_keys(rng, n)
+    vals = value_of(keys)
+    q_hit = keys[rng.permutation(n)]
+    q_miss = unique_keys(rng, n, exclude=keys)
+    return Workload("bulk", seed, a, b, dict(keys=keys, vals=vals, q_hit=q_hit, q_miss=q_miss))
+
+
+def mixed_batch(rng: SplitMix64, present: np.ndarray, fresh: np.ndarray, absent: np.ndarray,
+                n_ins: int, n_del: int, n_hit: int, n_miss: int):
+    """One concurrent batch: n_ins inserts of `fresh` keys, n_del deletes of distinct present
+    keys, n_hit searches of present keys, n_miss searches of `absent` keys, shuffled.
+    Returns (ops uint8, keys uint32, vals uint32)."""
+    assert fresh.size >= n_ins and absent.size >= n_miss
+    pi = rng.permutation(present.size)
+    dels = present[pi[:n_del]]
+    hits = present[rng.below(n_hit, present.size)] if n_hit else np.empty(0, np.uint32)
+    miss = absent[rng.below(n_miss, absent.size)] if n_miss else np.empty(0, np.uint32)
+    ins = fresh[:n_ins]
+    keys = np.concatenate([ins, dels, hits, miss]).astype(np.uint32)
+    ops = np.concatenate([np.full(n_ins, OP_INSERT), np.full(n_del, OP_DELETE),
+                          np.full(n_hit + n_miss, OP_SEARCH)]).astype(np.uint8)
+    perm = rng.permutation(keys.size)
+    keys, ops = keys[perm], ops[perm]
+    vals = value_of(keys)
+    return ops, keys, vals
+
+
+def gamma_counts(length: int, fractions) -> tuple[int, int, int, int]:
+    """Split a batch length over (insert new, delete existing, search existing, search absent)
+    as in the paper's operation distribution Gamma = (a, b, c, d)."""
+    a, b, c, d = fractions
+    n_ins = int(math.floor(a * length))
+    n_del = int(math.floor(b * length))
+    rest = length - n_ins - n_del
+    if c + d > 0:
+        n_hit = int(round(rest * c / (c + d)))
+    else:
+        n_hit = 0
+    return n_ins, n_del, n_hit, rest - n_hit

@@ -1,0 +1,312 @@
+"""Pins for the CPU oracle, each against something other than the oracle itself:
+
+- a literal slab-list simulation (lists of M-spot slabs walked head to tail) on tiny inputs;
+- closed forms of the universal hash in special cases fixed by modular arithmetic;
+- a hand-worked example written from the paper's operation definitions (tests/golden);
+- the utilisation values the paper prints for its 15-pair, 128-byte slabs (tests/golden);
+- the Binomial model of bucket loads under a uniform hash (mean slab count, chi-square);
+- invariants: no lost inserts, deleted keys absent, pool slabs = sum of (slabs - 1).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1710_11246_amd import workload as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EMPTY = 0xFFFFFFFF
+
+
+# ---------------------------------------------------------------------------------------------
+# Literal slab-list model: each bucket is a Python list of slabs, each slab a list of M spots
+# (None = empty, else [key, value, live]). Operations walk the list from its head the way the
+# paper describes them; nothing here counts with a formula.
+
+class SlabListModel:
+    def __init__(self, bucket_of, B, M, pool=None):
+        self.bucket_of, self.M, self.pool = bucket_of, M, pool
+        self.lists = [[[None] * M] for _ in range(B)]
+        self.pool_used = 0
+        self.err = 0
+
+    def replace(self, k, v):
+        if k == EMPTY:
+            self.err |= 1
+            return 0
+        slabs = self.lists[self.bucket_of(k)]
+        first_empty = None
+        for slab in slabs:
+            for i, spot in enumerate(slab):
+                if spot is None:
+                    if first_empty is None:
+                        first_empty = (slab, i)
+                elif spot[2] and spot[0] == k:
+                    spot[1] = v
+                    return 2
+        if first_empty is None:
+            if self.pool is not None and self.pool_used >= self.pool:
+                self.err |= 2
+                return 0
+            slabs.append([None] * self.M)
+            self.pool_used += 1
+            first_empty = (slabs[-1], 0)
+        slab, i = first_empty
+        slab[i] = [k, v, True]
+        return 1
+
+    def delete(self, k):
+        if k == EMPTY:
+            self.err |= 1
+            return 0
+        for slab in self.lists[self.bucket_of(k)]:
+            for spot in slab:
+                if spot is not None and spot[2] and spot[0] == k:
+                    spot[2] = False
+                    return 1
+        return 0
+
+    def search(self, k):
+        if k == EMPTY:
+            self.err |= 1
+            return 0, EMPTY, 0
+        slabs = self.lists[self.bucket_of(k)]
+        for j, slab in enumerate(slabs):
+            for spot in slab:
+                if spot is not None and spot[2] and spot[0] == k:
+                    return 1, spot[1], j + 1
+        return 0, EMPTY, len(slabs)
+
+    def stats(self):
+        live = [sum(1 for s in l for p in s if p is not None and p[2]) for l in self.lists]
+        tomb = [sum(1 for s in l for p in s if p is not None and not p[2]) for l in self.lists]
+        slabs = [len(l) for l in self.lists]
+        return live, tomb, slabs
+
+    def dump(self):
+        out = []
+        for b, l in enumerate(self.lists):
+            for s in l:
+                for p in s:
+                    if p is not None and p[2]:
+                        out.append((b, p[0], p[1]))
+        return sorted(out)
+
+
+@pytest.mark.parametrize("B,M", [(1, 1), (1, 3), (2, 2), (3, 1), (3, 31), (7, 2), (7, 3)])
+def test_oracle_matches_slab_list_model(oracle_mod, B, M):
+    rng = W.SplitMix64(1000 + 10 * B + M)
+    for trial in range(60):
+        pool = None if trial % 3 else int(rng.below(1, 4)[0])
+        a, b = W.hash_params(rng, oracle_mod.PRIME)
+        o = oracle_mod.Oracle(B, M, a, b, pool_slabs=pool)
+        model = SlabListModel(lambda k: int(o.bucket_of([k])[0]), B, M, pool)
+        n_ops = 80
+        domain = int(rng.below(1, 14)[0]) + 2
+        ops = rng.below(n_ops, 3).astype(np.uint8)
+        keys = rng.below(n_ops, domain).astype(np.uint32)
+        keys[rng.below(n_ops, 40) == 0] = EMPTY  # occasional reserved key
+        vals = (rng.next(n_ops) >> np.uint64(32)).astype(np.uint32)
+        got_v, got_s = o.mixed(ops, keys, vals)
+        for i in range(n_ops):
+            k, v = int(keys[i]), int(vals[i])
+            if ops[i] == 0:
+                f, mv, _ = model.search(k)
+                assert (got_s[i], got_v[i]) == (f, mv), (trial, i)
+            elif ops[i] == 1:
+                assert got_s[i] == model.replace(k, v), (trial, i)
+            else:
+                assert got_s[i] == model.delete(k), (trial, i)
+        live, tomb, slabs = o.bucket_stats()
+        ml, mt, ms = model.stats()
+        assert list(live) == ml and list(tomb) == mt and list(slabs) == ms
+        assert o.pool_used == model.pool_used == sum(s - 1 for s in ms)
+        assert o.error == model.err
+        db, dk, dv = o.dump()
+        assert sorted(zip(db.tolist(), dk.tolist(), dv.tolist())) == model.dump()
+        # slabs visited by a search, against the walk
+        probe = np.arange(domain, dtype=np.uint32)
+        _, _, visits = o.search(probe)
+        assert [model.search(int(k))[2] for k in probe] == visits.tolist()
+
+
+# ---------------------------------------------------------------------------------------------
+# Hash special cases: h(k) = ((a k + b) mod p) mod B with p = 2^32 - 5.
+
+def test_hash_closed_forms(oracle_mod):
+    p = oracle_mod.PRIME
+    assert p == 2**32 - 5
+    B = 1000
+    o = oracle_mod.Oracle(B, 31, 1, 0)
+    k = np.array([0, 1, 999, 1000, 123456789, p - 1, p, p + 1, p + 3, 2**32 - 2], np.uint32)
+    # a = 1, b = 0: identity below p, and keys at or above p wrap to k - p.
+    want = [int(x) % B if x < p else (int(x) - p) % B for x in k]
+    assert o.bucket_of(k).tolist() == want
+    # a = 2: 2 * (p+1)/2 = p + 1 = 1 (mod p).
+    o2 = oracle_mod.Oracle(B, 31, 2, 0)
+    assert o2.bucket_of([(p + 1) // 2]).tolist() == [1]
+    # b = p - 1 = -1 (mod p): key 1 maps to 0, key 0 to (p - 1) mod B.
+    o3 = oracle_mod.Oracle(B, 31, 1, p - 1)
+    assert o3.bucket_of([1, 0]).tolist() == [0, (p - 1) % B]
+    # a = p - 1 = -1 (mod p): h(k) = (p - k) mod B for 0 < k < p.
+    o4 = oracle_mod.Oracle(B, 31, p - 1, 0)
+    ks = np.array([1, 2, 77777, 2**31], np.uint32)
+    assert o4.bucket_of(ks).tolist() == [(p - int(x)) % B for x in ks]
+    # B = 1: everything in bucket 0.
+    o5 = oracle_mod.Oracle(1, 31, 12345, 678)
+    assert set(o5.bucket_of(np.arange(1000, dtype=np.uint32)).tolist()) == {0}
+    # the full 64-bit product: a k + b exceeds 2^32 and must not be truncated before mod p.
+    a, kk = 3_000_000_000, 4_000_000_000
+    o6 = oracle_mod.Oracle(2**31 + 11, 31, a, 7)
+    assert int(o6.bucket_of([kk])[0]) == ((a * kk + 7) % p) % (2**31 + 11)
+
+
+def test_invalid_parameters_rejected(oracle_mod):
+    p = oracle_mod.PRIME
+    for B, M, a, b in [(0, 31, 1, 0), (4, 0, 1, 0), (4, 31, 0, 0), (4, 31, p, 0), (4, 31, 1, p)]:
+        with pytest.raises(ValueError):
+            oracle_mod.Oracle(B, M, a, b)
+
+
+# ---------------------------------------------------------------------------------------------
+# Hand-worked example from the paper's definitions.
+
+def test_worked_example(oracle_mod):
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    o = oracle_mod.Oracle(g["num_buckets"], g["slab_elems"], g["hash_a"], g["hash_b"],
+                          pool_slabs=g["pool_slabs"])
+    for st in g["steps"]:
+        if st["op"] == "replace":
+            assert o.replace([st["key"]], [st["val"]]).tolist() == [st["status"]], st
+        elif st["op"] == "delete":
+            assert o.delete([st["key"]]).tolist() == [st["status"]], st
+        else:
+            v, f, vis = o.search([st["key"]])
+            assert (int(f[0]), int(v[0]), int(vis[0])) == \
+                (st["status"], st["val"], st["slabs_visited"]), st
+    fin = g["final"]
+    live, tomb, slabs = o.bucket_stats()
+    assert live.tolist() == fin["live"] and tomb.tolist() == fin["deleted"]
+    assert slabs.tolist() == fin["slabs"] and o.pool_used == fin["pool_used"]
+    assert o.error == oracle_mod.ERR_RESERVED | oracle_mod.ERR_NOMEM
+    b, k, v = o.dump()
+    assert sorted(zip(b.tolist(), k.tolist(), v.tolist())) == [tuple(x) for x in fin["dump_sorted"]]
+    assert abs(o.utilisation(8, 8) - fin["utilisation_x8_y8"]) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------------
+# The paper's printed utilisation figures (15 pairs per 128-byte slab).
+
+def test_paper_utilisation_points(oracle_mod):
+    g = json.load(open(os.path.join(GOLDEN, "paper_utilisation.json")))
+    n = 1 << g["n_log2"]
+    M = g["slab_elems"]
+    rng = W.SplitMix64(2017)
+    keys = W.unique_keys(rng, n)
+    a, b = W.hash_params(rng, oracle_mod.PRIME)
+    for pt in g["points"]:
+        B = int(round(n / (M * pt["beta"])))
+        o = oracle_mod.Oracle(B, M, a, b)
+        assert (o.replace(keys, keys) == 1).all()
+        u = o.utilisation(g["elem_bytes"], g["overhead_bytes"])
+        assert abs(u - pt["u"]) <= pt["tol"], (pt, u)
+    # maximum utilisation as B -> 1: one bucket whose slabs are all full
+    o = oracle_mod.Oracle(1, M, a, b)
+    o.replace(keys[:M * 200], keys[:M * 200])
+    u = o.utilisation(g["elem_bytes"], g["overhead_bytes"])
+    assert abs(u - g["max_utilisation"]["u"]) <= g["max_utilisation"]["tol"]
+
+
+# ---------------------------------------------------------------------------------------------
+# Binomial model of a uniform hash.
+
+def _expected_slabs(n, B, M):
+    from scipy.stats import binom
+    xs = np.arange(0, int(n / B + 12 * math.sqrt(n / B) + 4 * M + 64))
+    pmf = binom.pmf(xs, n, 1.0 / B)
+    slabs = np.maximum(1, -(-xs // M))
+    return float((pmf * slabs).sum()), float((pmf * slabs * slabs).sum())
+
+
+@pytest.mark.parametrize("B", [261962, 176200, 55174])
+def test_mean_slab_count_matches_binomial_model(oracle_mod, B):
+    n, M = 1 << 22, 31
+    rng = W.SplitMix64(4242)
+    keys = W.unique_keys(rng, n)
+    a, b = W.hash_params(rng, oracle_mod.PRIME)
+    o = oracle_mod.Oracle(B, M, a, b)
+    o.replace(keys, W.value_of(keys))
+    mean = o.total_slabs / B
+    e1, e2 = _expected_slabs(n, B, M)
+    se = math.sqrt(max(e2 - e1 * e1, 1e-12) / B)
+    assert abs(mean - e1) <= max(5e-4 * e1, 4 * se), (mean, e1, se)
+    # unsuccessful searches read every slab of their bucket: mean visits = E[slabs]
+    miss = W.unique_keys(rng, 1 << 16, exclude=keys)
+    _, found, visits = o.search(miss)
+    assert not found.any()
+    se_m = math.sqrt(max(e2 - e1 * e1, 1e-12) / miss.size)
+    assert abs(visits.mean() - e1) <= 5 * se_m + 1e-9
+
+
+def test_bucket_loads_chi_square(oracle_mod):
+    from scipy.stats import chi2
+    n, B = 1 << 20, 4096
+    rng = W.SplitMix64(99)
+    keys = W.unique_keys(rng, n)
+    a, b = W.hash_params(rng, oracle_mod.PRIME)
+    o = oracle_mod.Oracle(B, 31, a, b)
+    counts = np.bincount(o.bucket_of(keys), minlength=B)
+    e = n / B
+    stat = float(((counts - e) ** 2 / e).sum())
+    pval = chi2.sf(stat, B - 1)
+    assert 1e-4 < pval < 1 - 1e-4, (stat, pval)
+
+
+# ---------------------------------------------------------------------------------------------
+# Invariants on a mid-size phased workload.
+
+def test_phased_invariants(oracle_mod):
+    wl = W.phased(seed=1, n=1 << 16, n_queries=1 << 16, hit_fraction=0.5,
+                  delete_fraction=0.25, prime=oracle_mod.PRIME)
+    o = oracle_mod.Oracle(1 << 12, 31, wl.hash_a, wl.hash_b)
+    assert (o.replace(wl["keys"], wl["vals"]) == 1).all()           # unique keys: all new
+    v, f, _ = o.search(wl["keys"])
+    assert f.all() and (v == wl["vals"]).all()                      # no lost inserts
+    v, f, _ = o.search(wl["miss"])
+    assert not f.any() and (v == EMPTY).all()
+    assert (o.delete(wl["deletes"]) == 1).all()
+    assert (o.delete(wl["deletes"]) == 0).all()                     # second delete: absent
+    v, f, _ = o.search(wl["deletes"])
+    assert not f.any()                                              # deleted keys absent
+    live, tomb, slabs = o.bucket_stats()
+    assert live.sum() == wl["keys"].size - wl["deletes"].size
+    assert tomb.sum() == wl["deletes"].size
+    assert o.pool_used == int((slabs - 1).sum())
+    # re-inserting deleted keys appends (deleted spots are not reused): occupancy grows
+    occ_before = live + tomb
+    assert (o.replace(wl["deletes"], wl["deletes"]) == 1).all()
+    live2, tomb2, _ = o.bucket_stats()
+    assert ((live2 + tomb2) - occ_before).sum() == wl["deletes"].size
+    # flush drops deleted spots and releases slabs
+    o.flush_all()
+    live3, tomb3, slabs3 = o.bucket_stats()
+    assert tomb3.sum() == 0 and (live3 == live2).all()
+    assert o.pool_used == int((slabs3 - 1).sum())
+    v, f, _ = o.search(wl["keys"])
+    assert f.all()
+
+
+def test_splitmix64_matches_big_int_definition():
+    def mix(z):
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & (2**64 - 1)
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & (2**64 - 1)
+        return z ^ (z >> 31)
+    seed = 0xDEADBEEF12345678
+    r = W.SplitMix64(seed)
+    got = r.next(5).tolist() + r.next(3).tolist()
+    want = [mix((seed + i * 0x9E3779B97F4A7C15) & (2**64 - 1)) for i in range(1, 9)]
+    assert got == want
+    keys = W.unique_keys(W.SplitMix64(5), 10000)
+    assert np.unique(keys).size == 10000 and (keys != EMPTY).all()
