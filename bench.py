@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Slab-hash benchmark on one MI355X.
+
+One step is one pass of the whole hot path over one batch of synthetic input:
+  reset the table (initialise base slabs, pool and bitmaps),
+  bulk build of 2^22 unique uniform uint32 key/value pairs (value = SplitMix64 finaliser of the
+  key) into B buckets, 2^22 all-hit searches (a permutation of the keys), 2^22 all-miss searches
+  (fresh keys), then 16 concurrent mixed batches of 2^16 ops with the paper's operation
+  distribution Gamma1 = (0.2 insert new, 0.2 delete existing, 0.3 search existing, 0.3 search
+  absent), shuffled.
+value = all ops of a step / step time, in M ops/s. Per-kernel durations come from HIP events
+on the launch stream inside the timed region; the roofline entry uses the algorithmic bytes of
+the kernel that takes most of the step.
+
+python bench.py [--steps K] [--warmup W] [--util 0.6] [--no-cpu-baseline] [--sweep]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_KEYS = 1 << 22
+MIX_BATCH = 1 << 16
+MIX_BATCHES = 16
+GAMMA1 = (0.2, 0.2, 0.3, 0.3)
+# Largest bucket counts whose Binomial-model utilisation reaches each target for n = 2^22 and
+# 31 pairs per 256-byte slab (the same model the autotuner evaluates).
+B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0.7: 176200,
+              0.8: 55174}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def chain_visits(occ: np.ndarray, m: int = 31) -> float:
+    """Total slabs read to reach every occupied slot once (slot p of a list sits in slab p//m)."""
+    occ = occ.astype(np.int64)
+    full, rem = occ // m, occ % m
+    # slots in complete slabs: m * (1 + 2 + ... + full), the remainder sits in slab full + 1
+    return float((m * full * (full + 1) // 2 + rem * (full + 1)).sum())
+
+
+def make_inputs(util: float, seed: int = 11):
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    wl = W.bulk(seed=seed, n=N_KEYS, prime=S.SH_HASH_PRIME)
+    rng = W.SplitMix64(seed ^ 0xABCDEF)
+    n_ins, n_del, n_hit, n_miss = W.gamma_counts(MIX_BATCH, GAMMA1)
+    fresh = W.unique_keys(rng, n_ins * MIX_BATCHES, exclude=np.concatenate(
+        [wl["keys"], wl["q_miss"]]))
+    present = wl["keys"].copy()
+    batches = []
+    for bi in range(MIX_BATCHES):
+        ops, bk, bv = W.mixed_batch(rng, present, fresh[bi * n_ins:(bi + 1) * n_ins],
+                                    wl["q_miss"], n_ins, n_del, n_hit, n_miss)
+        batches.append((ops, bk, bv))
+        dels = bk[ops == 2]
+        present = np.concatenate([present[~np.isin(present, dels)], bk[ops == 1]])
+    return wl, batches
+
+
+def cpu_baseline(wl, batches, B):
+    """The CPU oracle (single-threaded C) over one whole step on the host."""
+    import oracle
+    from paper_1710_11246_amd import slabhash as S
+    t0 = time.perf_counter()
+    o = oracle.Oracle(B, S.SH_SLAB_PAIRS, wl.hash_a, wl.hash_b)
+    o.replace(wl["keys"], wl["vals"])
+    o.search(wl["q_hit"])
+    o.search(wl["q_miss"])
+    for ops, bk, bv in batches:
+        o.mixed(ops, bk, bv)
+    dt = time.perf_counter() - t0
+    n_ops = 3 * N_KEYS + MIX_BATCHES * MIX_BATCH
+    return {"value": round(n_ops / dt / 1e6, 3), "unit": "M ops/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "one full step on one host core: build 2^22, 2^22 hit + 2^22 miss "
+                      "searches, 16 mixed batches of 2^16 (%.1f s)" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--util", type=float, default=0.6, choices=sorted(B_FOR_UTIL))
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time build/search at every utilisation target")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the slab hash here is built and timed on a "
+              "single MI355X (multi-GPU sharding is a design note, not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    S.lib()
+
+    B = B_FOR_UTIL[args.util]
+    log("generating inputs (n=2^22, B=%d)" % B)
+    wl, batches = make_inputs(args.util)
+    n_ins, n_del, n_hit, n_miss = W.gamma_counts(MIX_BATCH, GAMMA1)
+    pool = S.pool_slabs_bound(N_KEYS + n_ins * MIX_BATCHES)
+    table = S.SlabHash(B, pool, wl.hash_a, wl.hash_b)
+    if args.waves_per_cu:
+        table.set_launch(args.waves_per_cu)
+    h = table.handle
+    dev = "cuda"
+    keys, vals = S.to_dev(wl["keys"]), S.to_dev(wl["vals"])
+    q_hit, q_miss = S.to_dev(wl["q_hit"]), S.to_dev(wl["q_miss"])
+    st_build = torch.empty(N_KEYS, dtype=torch.uint8, device=dev)
+    v_out = torch.empty(N_KEYS, dtype=torch.int32, device=dev)
+    f_out = torch.empty(N_KEYS, dtype=torch.uint8, device=dev)
+    mix_dev = [(S.to_dev(o), S.to_dev(k), S.to_dev(v)) for o, k, v in batches]
+    mv_out = torch.empty(MIX_BATCH, dtype=torch.int32, device=dev)
+    ms_out = torch.empty(MIX_BATCH, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    names = ["reset", "build", "search_hit", "search_miss", "mixed"]
+    ev = {k: [] for k in names}
+
+    def timed(name, fn, record):
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            ev[name].append((e0, e1))
+        else:
+            fn()
+
+    def step(record):
+        timed("reset", lambda: S.sh_reset(h, stream), record)
+        timed("build", lambda: S.sh_build(h, keys, vals, st_build, stream), record)
+        timed("search_hit", lambda: S.sh_search(h, q_hit, v_out, f_out, stream), record)
+        timed("search_miss", lambda: S.sh_search(h, q_miss, v_out, f_out, stream), record)
+        for o, k, v in mix_dev:
+            timed("mixed", lambda: S.sh_mixed(h, o, k, v, mv_out, ms_out, stream), record)
+
+    log("warmup %d steps" % args.warmup)
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log("timing %d steps" % args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log("timed region done")
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    ops_step = 3 * N_KEYS + MIX_BATCHES * MIX_BATCH
+    value = ops_step / ((t1 - t0) / args.steps) / 1e6
+
+    avg_ms = {k: (sum(a.elapsed_time(b) for a, b in v) / len(v)) for k, v in ev.items()}
+    per_step_ms = {k: avg_ms[k] * (MIX_BATCHES if k == "mixed" else 1) for k in avg_ms}
+
+    # Structure of the built table (before the mixed batches) for the byte accounting.
+    S.sh_reset(h, stream)
+    S.sh_build(h, keys, vals, st_build, stream)
+    assert bool((st_build == 1).all())
+    stats_built = table.stats()
+    _, _, _, counts, viol = table.dump()
+    assert viol == 0
+    occ = counts[:, 0].astype(np.int64) + counts[:, 1]
+    v_hit = chain_visits(occ) / N_KEYS
+    v_miss = float(counts[:, 2].mean())
+    new_slabs = stats_built["pool_allocated"]
+    util = 8.0 * stats_built["live"] / (256.0 * stats_built["slabs_total"])
+
+    # Algorithmic bytes per launch ("Roofline and algorithmic bytes").
+    bytes_l = {
+        "build": N_KEYS * (8 + 1 + 8) + 256.0 * v_hit * N_KEYS + new_slabs * (4 + 4),
+        "search_hit": N_KEYS * (4 + 4 + 1) + 256.0 * v_hit * N_KEYS,
+        "search_miss": N_KEYS * (4 + 4 + 1) + 256.0 * v_miss * N_KEYS,
+        "mixed": MIX_BATCH * (1 + 4 + 4 + 4 + 1) + 256.0 * (
+            (n_ins + n_miss) * v_miss + (n_del + n_hit) * v_hit) + 8.0 * (n_ins + n_del),
+        "reset": float(table.storage.numel()),
+    }
+    kernels = {}
+    for k in names:
+        gbs = bytes_l[k] / (avg_ms[k] * 1e-3) / 1e9
+        n_ops = {"build": N_KEYS, "search_hit": N_KEYS, "search_miss": N_KEYS,
+                 "mixed": MIX_BATCH}.get(k, 0)
+        kernels[k] = {"avg_ms": round(avg_ms[k], 4), "ms_per_step": round(per_step_ms[k], 4),
+                      "algorithmic_GBps": round(gbs, 1),
+                      "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        if n_ops:
+            kernels[k]["Mops"] = round(n_ops / (avg_ms[k] * 1e-3) / 1e6, 1)
+    dom = max((k for k in names if k != "reset"), key=lambda k: per_step_ms[k])
+    ach = bytes_l[dom] / (avg_ms[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "bytes_per_launch": int(bytes_l[dom])}
+
+    sweep = None
+    if args.sweep:
+        sweep = {}
+        for u, Bu in sorted(B_FOR_UTIL.items()):
+            tu = S.SlabHash(Bu, S.pool_slabs_bound(N_KEYS), wl.hash_a, wl.hash_b)
+            res = {}
+            for rep in range(4):
+                tu.reset()
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                e[0].record()
+                S.sh_build(tu.handle, keys, vals, st_build)
+                e[1].record()
+                S.sh_search(tu.handle, q_hit, v_out, f_out)
+                e[2].record()
+                S.sh_search(tu.handle, q_miss, v_out, f_out)
+                e[3].record()
+                torch.cuda.synchronize()
+                if rep:
+                    for i, nm in enumerate(["build", "search_hit", "search_miss"]):
+                        res.setdefault(nm, []).append(e[i].elapsed_time(e[i + 1]))
+            s_u = tu.stats()
+            sweep[str(u)] = {"num_buckets": Bu,
+                             "utilisation": round(8.0 * s_u["live"] / (256.0 * s_u["slabs_total"]), 4),
+                             **{nm: round(N_KEYS / (float(np.median(v)) * 1e-3) / 1e6, 1)
+                                for nm, v in res.items()}}
+            del tu
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(wl, batches, B)
+
+    out = {
+        "metric": "M ops/s build/search/mixed at 2^22 keys vs HBM peak",
+        "value": round(value, 2),
+        "unit": "M ops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "slab hash step: reset + bulk build 2^22 uniform uint32 keys + 2^22 "
+                        "all-hit + 2^22 all-miss searches + 16 concurrent Gamma1 batches of 2^16",
+            "keys": N_KEYS, "num_buckets": B, "target_utilisation": args.util,
+            "achieved_utilisation": round(util, 4), "pool_slabs": pool,
+            "mixed_batches": MIX_BATCHES, "mixed_batch_ops": MIX_BATCH,
+            "ops_per_step": ops_step, "slabs_per_hit": round(v_hit, 4),
+            "slabs_per_miss": round(v_miss, 4),
+        },
+        "kernels": kernels,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if sweep is not None:
+        out["sweep"] = sweep
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,162 @@
+/*
+ * slabhash.h -- C ABI of an MI355X (gfx950) slab hash: the dynamic GPU hash table of
+ * Ashkiani, Farach-Colton and Owens, "A Dynamic Hash Table for the GPU" (IPDPS 2018).
+ *
+ * The table is a direct-address array of B base slabs ("Slab Hash" subsection), each the head
+ * of a slab list ("Slab list" subsection). Slabs are 256 bytes: 31 key/value slots of 8 bytes
+ * (key in the low 32 bits, value in the high 32 bits), then one 8-byte word holding an auxiliary
+ * 32-bit field and the 32-bit index of the next slab. Extra slabs come from a pool managed by a
+ * wavefront-synchronous bitmap allocator in blocks of 2048 slabs ("Dynamic memory allocation",
+ * SlabAlloc with all blocks in one contiguous array). A wavefront of 64 lanes processes the
+ * operations its lanes hold one at a time ("warp-cooperative work sharing").
+ *
+ * Conventions for every call:
+ *   - Pointers prefixed d_ are device pointers, caller-owned; the library never allocates or
+ *     frees device memory. h_ pointers are host memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream). Operation calls are asynchronous:
+ *     the caller keeps buffers alive until the stream has passed the call.
+ *   - Keys are uint32 in [0, 0xFFFFFFFE]; 0xFFFFFFFF is reserved (the empty marker). Values
+ *     are any uint32.
+ *   - Argument errors (NULL where not allowed, zero buckets, storage too small or not 256-byte
+ *     aligned, n >= 2^32) return SH_EINVAL before anything is enqueued; n == 0 is a no-op.
+ *   - Errors found on the device (a reserved key in the input, pool exhausted) do not stop the
+ *     call: the affected op gets status 0 (found 0, value 0xFFFFFFFF for a search) and a bit is
+ *     set in the table's sticky error word, read by sh_stats.
+ *   - sh_search, sh_insert, sh_delete and sh_mixed may run concurrently on one table from
+ *     different streams; sh_search reads through caches and is exact for updates ordered
+ *     before it, sh_mixed reads coherently and is linearizable against concurrent updates.
+ *     sh_create, sh_reset, sh_stats and sh_dump must not overlap any other call on
+ *     the same table.
+ *   - Per-op status: search 1 found / 0 not found; insert 1 new key / 2 replaced the value of
+ *     an existing key / 0 failed; delete 1 deleted / 0 absent or failed.
+ */
+#ifndef SLABHASH_H
+#define SLABHASH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SH_OK = 0,
+    SH_EINVAL = 1, /* bad argument; nothing enqueued */
+    SH_ENOMEM = 2, /* host-side allocation of the table handle failed */
+    SH_EHIP = 3,   /* a HIP runtime call failed */
+    SH_EBUSY = 4   /* resource busy (server admission) */
+} sh_status_t;
+
+/* Op codes of sh_mixed. */
+enum { SH_OP_SEARCH = 0, SH_OP_INSERT = 1, SH_OP_DELETE = 2 };
+
+/* Bits of the sticky device error word. */
+enum { SH_ERR_RESERVED_KEY = 1u, SH_ERR_POOL_EXHAUSTED = 2u };
+
+#define SH_EMPTY_KEY 0xFFFFFFFFu
+#define SH_HASH_PRIME 4294967291u /* p of the bucket hash, the largest prime below 2^32 */
+#define SH_SLAB_BYTES 256u
+#define SH_SLAB_PAIRS 31u
+#define SH_BLOCK_SLABS 2048u /* pool slabs per allocator block (one 256-byte bitmap) */
+
+/* Table geometry and hash ("Slab Hash" subsection): bucket(k) = ((a k + b) mod p) mod B. */
+typedef struct {
+    uint32_t num_buckets; /* B >= 1 */
+    uint32_t pool_slabs;  /* slabs beyond the base slabs; a multiple of SH_BLOCK_SLABS, may be 0 */
+    uint32_t hash_a;      /* 1 <= a < p */
+    uint32_t hash_b;      /* 0 <= b < p */
+} sh_params_t;
+
+/* Launch shape of the operation kernels: persistent grid of waves_per_cu * (compute units)
+   wavefronts (0 = library default). Never changes results. */
+typedef struct {
+    uint32_t waves_per_cu;
+    uint32_t reserved[3];
+} sh_launch_t;
+
+typedef struct sh_table sh_table_t; /* opaque host handle */
+
+typedef struct {
+    uint64_t live;           /* live key/value pairs */
+    uint64_t tombstones;     /* deleted slots still occupying space */
+    uint64_t slabs_total;    /* base slabs + linked pool slabs */
+    uint64_t pool_allocated; /* set bits in the allocator bitmaps */
+    uint64_t pool_capacity;  /* pool_slabs */
+    uint32_t error_word;     /* SH_ERR_* bits raised since create/reset */
+    uint32_t violations;     /* structure-invariant violations seen by the walk (0 expected) */
+    uint32_t num_buckets, hash_a, hash_b, hash_p;
+} sh_stats_t;
+
+/* Device bytes a table with these parameters needs (header + base slabs + pool + bitmaps).
+   Returns 0 for invalid parameters. */
+size_t sh_storage_bytes(const sh_params_t *p);
+
+/* Bind a table to caller-owned device storage (256-byte aligned, at least sh_storage_bytes)
+   and enqueue its initialisation on `stream`: every slot empty, every next pointer empty, all
+   pool slabs free, error word cleared. On success *out receives a host handle. */
+sh_status_t sh_create(const sh_params_t *p, void *d_storage, size_t bytes, void *stream,
+                      sh_table_t **out);
+
+/* Re-initialise the table in place (same as the initialisation done by sh_create). */
+sh_status_t sh_reset(sh_table_t *t, void *stream);
+
+/* Free the host handle only; the device storage stays the caller's. */
+sh_status_t sh_destroy(sh_table_t *t);
+
+/* Set the launch shape used by later calls on this table (NULL restores the default). */
+sh_status_t sh_set_launch(sh_table_t *t, const sh_launch_t *shape);
+
+/* Bulk build: insert n pairs, each lane of a wavefront holding one ("Bulk benchmarks"; the
+   paper notes a bulk build and an incremental batch insertion are the same operation). Uses
+   REPLACE semantics ("Supported Operations": replace the value of an existing key, else insert
+   at the first empty slot, linking a new slab when the tail is full). d_status may be NULL. */
+sh_status_t sh_build(sh_table_t *t, const uint32_t *d_keys, const uint32_t *d_vals, uint64_t n,
+                     uint8_t *d_status, void *stream);
+
+/* Incremental insertion of a batch ("Incremental insertion" experiment): same semantics and
+   kernel as sh_build. */
+sh_status_t sh_insert(sh_table_t *t, const uint32_t *d_keys, const uint32_t *d_vals,
+                      uint64_t n, uint8_t *d_status, void *stream);
+
+/* DELETE ("Deletion" subsection): the matching slot becomes a tombstone (never empty again, so
+   not reused). Absent keys give status 0. d_status may be NULL. */
+sh_status_t sh_delete(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint8_t *d_status,
+                      void *stream);
+
+/* SEARCH ("Search" subsection): d_vals_out[i] = value of d_keys[i], or 0xFFFFFFFF if absent.
+   d_found (may be NULL) gets 1/0; it is authoritative since a stored value may be 0xFFFFFFFF. */
+sh_status_t sh_search(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint32_t *d_vals_out,
+                      uint8_t *d_found, void *stream);
+
+/* Concurrent mixed batch ("Concurrent benchmarks"): d_ops[i] in {SH_OP_SEARCH, SH_OP_INSERT,
+   SH_OP_DELETE} applies to d_keys[i] (and d_vals_in[i] for inserts); all ops of the batch run
+   concurrently and the outcome is linearizable. d_vals_out[i] gets the search result
+   (0xFFFFFFFF for non-search ops), d_status[i] the op's status. Unknown op codes give status 0. */
+sh_status_t sh_mixed(sh_table_t *t, const uint8_t *d_ops, const uint32_t *d_keys,
+                     const uint32_t *d_vals_in, uint64_t n, uint32_t *d_vals_out,
+                     uint8_t *d_status, void *stream);
+
+/* Walk every bucket and return totals, allocator occupancy and the error word in *h_out.
+   Synchronises `stream`. */
+sh_status_t sh_stats(sh_table_t *t, sh_stats_t *h_out, void *stream);
+
+/* Walk every bucket and emit each live pair as (bucket, key, value) into the device arrays
+   (at most cap entries, in no particular order); *d_count (device uint64) receives the number
+   of live pairs even if larger than cap. d_bucket_counts (may be NULL) receives, per bucket,
+   three uint32: live, tombstones, slabs. d_violations (device uint32, may be NULL) receives the
+   number of invariant violations found: an empty slot before a full one or in a non-tail
+   slab, a malformed auxiliary word, a next index out of range or not allocated, a chain that
+   does not end. Every output is written by the call (no pre-zeroing needed). */
+sh_status_t sh_dump(sh_table_t *t, uint32_t *d_bucket, uint32_t *d_key, uint32_t *d_val,
+                    uint64_t cap, uint32_t *d_bucket_counts, uint64_t *d_count,
+                    uint32_t *d_violations, void *stream);
+
+/* Short description of a status code. */
+const char *sh_strerror(sh_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLABHASH_H */

@@ -1,0 +1,320 @@
+"""Python binding of libslabhash.so (include/slabhash.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and only converts arguments:
+torch tensors (device memory) become pointers, a torch stream becomes a hipStream_t. All work
+runs in the HIP kernels of the library. The library is loaded on first use and a missing or
+unloadable library raises immediately; there is no other code path.
+
+Keys and values are uint32 bit patterns carried in torch.int32 tensors (torch has no general
+uint32 support); ops, statuses and found flags are torch.uint8.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libslabhash.so")
+HEADER_PATH = os.path.join(os.path.dirname(PKG), "include", "slabhash.h")
+
+SH_OK, SH_EINVAL, SH_ENOMEM, SH_EHIP, SH_EBUSY = 0, 1, 2, 3, 4
+SH_OP_SEARCH, SH_OP_INSERT, SH_OP_DELETE = 0, 1, 2
+SH_ERR_RESERVED_KEY, SH_ERR_POOL_EXHAUSTED = 1, 2
+SH_EMPTY_KEY = 0xFFFFFFFF
+SH_HASH_PRIME = 4294967291
+SH_SLAB_BYTES = 256
+SH_SLAB_PAIRS = 31
+SH_BLOCK_SLABS = 2048
+
+
+class ShParams(ctypes.Structure):
+    _fields_ = [("num_buckets", ctypes.c_uint32), ("pool_slabs", ctypes.c_uint32),
+                ("hash_a", ctypes.c_uint32), ("hash_b", ctypes.c_uint32)]
+
+
+class ShLaunch(ctypes.Structure):
+    _fields_ = [("waves_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+
+class ShStats(ctypes.Structure):
+    _fields_ = [("live", ctypes.c_uint64), ("tombstones", ctypes.c_uint64),
+                ("slabs_total", ctypes.c_uint64), ("pool_allocated", ctypes.c_uint64),
+                ("pool_capacity", ctypes.c_uint64), ("error_word", ctypes.c_uint32),
+                ("violations", ctypes.c_uint32), ("num_buckets", ctypes.c_uint32),
+                ("hash_a", ctypes.c_uint32), ("hash_b", ctypes.c_uint32),
+                ("hash_p", ctypes.c_uint32)]
+
+
+class SlabHashError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__("%s failed: %s (%d)" % (fn, sh_strerror(code), code))
+        self.code = code
+
+
+_P, _U32, _U64, _SZ = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+_SIGS = {
+    "sh_storage_bytes": ([_P], _SZ),
+    "sh_create": ([_P, _P, _SZ, _P, _P], ctypes.c_int),
+    "sh_reset": ([_P, _P], ctypes.c_int),
+    "sh_destroy": ([_P], ctypes.c_int),
+    "sh_set_launch": ([_P, _P], ctypes.c_int),
+    "sh_build": ([_P, _P, _P, _U64, _P, _P], ctypes.c_int),
+    "sh_insert": ([_P, _P, _P, _U64, _P, _P], ctypes.c_int),
+    "sh_delete": ([_P, _P, _U64, _P, _P], ctypes.c_int),
+    "sh_search": ([_P, _P, _U64, _P, _P, _P], ctypes.c_int),
+    "sh_mixed": ([_P, _P, _P, _P, _U64, _P, _P, _P], ctypes.c_int),
+    "sh_stats": ([_P, _P, _P], ctypes.c_int),
+    "sh_dump": ([_P, _P, _P, _P, _U64, _P, _P, _P, _P], ctypes.c_int),
+    "sh_strerror": ([ctypes.c_int], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libslabhash.so (built by paper_1710_11246_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libslabhash.so is not built (%s); run "
+                               "`python -m paper_1710_11246_amd.build` or __graft_entry__.build()"
+                               % LIB_PATH)
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(l, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = l
+    return _lib
+
+
+def declared_symbols() -> list[str]:
+    """Entry points declared in include/slabhash.h."""
+    text = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(sh_\w+)\s*\(", text, re.M)))
+
+
+def _check(fn: str, code: int) -> None:
+    if code != SH_OK:
+        raise SlabHashError(fn, code)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+_U32_TYPES = (torch.int32,) + ((torch.uint32,) if hasattr(torch, "uint32") else ())
+
+
+def _dev(t, name: str, dtypes, n: int | None = None, allow_none: bool = False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError("%s is required" % name)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype not in dtypes:
+        raise ValueError("%s has dtype %s, expected one of %s" % (name, t.dtype, dtypes))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if n is not None and t.numel() < n:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), n))
+    return t.data_ptr()
+
+
+def sh_strerror(code: int) -> str:
+    return lib().sh_strerror(int(code)).decode()
+
+
+def sh_storage_bytes(params: ShParams) -> int:
+    return int(lib().sh_storage_bytes(ctypes.byref(params)))
+
+
+def sh_create(params: ShParams, storage: torch.Tensor, stream=None) -> ctypes.c_void_p:
+    if not isinstance(storage, torch.Tensor) or not storage.is_cuda or \
+            not storage.is_contiguous():
+        raise ValueError("storage must be a contiguous CUDA tensor")
+    out = ctypes.c_void_p()
+    nbytes = storage.numel() * storage.element_size()
+    _check("sh_create", lib().sh_create(ctypes.byref(params), storage.data_ptr(), nbytes,
+                                        _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def sh_reset(t, stream=None) -> None:
+    _check("sh_reset", lib().sh_reset(t, _stream(stream)))
+
+
+def sh_destroy(t) -> None:
+    _check("sh_destroy", lib().sh_destroy(t))
+
+
+def sh_set_launch(t, waves_per_cu: int = 0) -> None:
+    shape = ShLaunch(int(waves_per_cu))
+    _check("sh_set_launch", lib().sh_set_launch(t, ctypes.byref(shape)))
+
+
+def sh_build(t, keys, vals, status=None, stream=None) -> None:
+    n = keys.numel()
+    _check("sh_build", lib().sh_build(
+        t, _dev(keys, "keys", _U32_TYPES), _dev(vals, "vals", _U32_TYPES, n), n,
+        _dev(status, "status", (torch.uint8,), n, True), _stream(stream)))
+
+
+def sh_insert(t, keys, vals, status=None, stream=None) -> None:
+    n = keys.numel()
+    _check("sh_insert", lib().sh_insert(
+        t, _dev(keys, "keys", _U32_TYPES), _dev(vals, "vals", _U32_TYPES, n), n,
+        _dev(status, "status", (torch.uint8,), n, True), _stream(stream)))
+
+
+def sh_delete(t, keys, status=None, stream=None) -> None:
+    n = keys.numel()
+    _check("sh_delete", lib().sh_delete(
+        t, _dev(keys, "keys", _U32_TYPES), n, _dev(status, "status", (torch.uint8,), n, True),
+        _stream(stream)))
+
+
+def sh_search(t, keys, vals_out, found=None, stream=None) -> None:
+    n = keys.numel()
+    _check("sh_search", lib().sh_search(
+        t, _dev(keys, "keys", _U32_TYPES), n, _dev(vals_out, "vals_out", _U32_TYPES, n),
+        _dev(found, "found", (torch.uint8,), n, True), _stream(stream)))
+
+
+def sh_mixed(t, ops, keys, vals_in, vals_out, status, stream=None) -> None:
+    n = keys.numel()
+    _check("sh_mixed", lib().sh_mixed(
+        t, _dev(ops, "ops", (torch.uint8,), n), _dev(keys, "keys", _U32_TYPES),
+        _dev(vals_in, "vals_in", _U32_TYPES, n), n, _dev(vals_out, "vals_out", _U32_TYPES, n),
+        _dev(status, "status", (torch.uint8,), n), _stream(stream)))
+
+
+def sh_stats(t, stream=None) -> dict:
+    st = ShStats()
+    _check("sh_stats", lib().sh_stats(t, ctypes.byref(st), _stream(stream)))
+    return {name: int(getattr(st, name)) for name, _ in ShStats._fields_}
+
+
+def sh_dump(t, bucket, key, val, bucket_counts, count, violations, stream=None) -> None:
+    cap = 0 if key is None else key.numel()
+    _check("sh_dump", lib().sh_dump(
+        t, _dev(bucket, "bucket", _U32_TYPES, cap, True), _dev(key, "key", _U32_TYPES, cap, True),
+        _dev(val, "val", _U32_TYPES, cap, True), cap,
+        _dev(bucket_counts, "bucket_counts", _U32_TYPES, None, True),
+        _dev(count, "count", (torch.int64,), 1), _dev(violations, "violations", _U32_TYPES, 1, True),
+        _stream(stream)))
+
+
+# ---------------------------------------------------------------------------------------------
+# Conveniences for tests and the benchmark (still only marshalling).
+
+def to_dev(a: np.ndarray, device="cuda") -> torch.Tensor:
+    """uint32/uint8 numpy array -> device tensor (int32 bit pattern for uint32)."""
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to(device)
+
+
+def to_host_u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def pool_slabs_bound(n_inserts: int, concurrency_slack_blocks: int = 4) -> int:
+    """A pool size (multiple of 2048) that holds every slab n_inserts new keys can need: a
+    bucket with c occupied slots uses ceil(c / 31) - 1 pool slabs <= c / 31, plus blocks of
+    slack for slabs held briefly by wavefronts that lose a link race."""
+    need = -(-int(n_inserts) // SH_SLAB_PAIRS)
+    blocks = -(-need // SH_BLOCK_SLABS) + concurrency_slack_blocks
+    return blocks * SH_BLOCK_SLABS
+
+
+class SlabHash:
+    """A table plus the torch tensor that holds its device storage."""
+
+    def __init__(self, num_buckets: int, pool_slabs: int, hash_a: int, hash_b: int,
+                 device="cuda", stream=None):
+        self.params = ShParams(int(num_buckets), int(pool_slabs), int(hash_a), int(hash_b))
+        nbytes = sh_storage_bytes(self.params)
+        if nbytes == 0:
+            raise ValueError("invalid table parameters")
+        self.storage = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.handle = sh_create(self.params, self.storage, stream)
+        self.device = device
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                sh_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def num_buckets(self) -> int:
+        return self.params.num_buckets
+
+    def reset(self, stream=None):
+        sh_reset(self.handle, stream)
+
+    def set_launch(self, waves_per_cu: int):
+        sh_set_launch(self.handle, waves_per_cu)
+
+    def insert(self, keys, vals, stream=None, status=True):
+        st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
+        sh_insert(self.handle, keys, vals, st, stream)
+        return st
+
+    def build(self, keys, vals, stream=None, status=True):
+        st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
+        sh_build(self.handle, keys, vals, st, stream)
+        return st
+
+    def delete(self, keys, stream=None):
+        st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        sh_delete(self.handle, keys, st, stream)
+        return st
+
+    def search(self, keys, stream=None):
+        v = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+        f = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        sh_search(self.handle, keys, v, f, stream)
+        return v, f
+
+    def mixed(self, ops, keys, vals, stream=None):
+        vo = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+        st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        sh_mixed(self.handle, ops, keys, vals, vo, st, stream)
+        return vo, st
+
+    def stats(self, stream=None) -> dict:
+        return sh_stats(self.handle, stream)
+
+    def dump(self, stream=None):
+        """Returns numpy (bucket, key, value) sorted by (bucket, key), per-bucket counts [B, 3]
+        (live, deleted, slabs), and the violation count."""
+        dev = self.device
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        viol = torch.zeros(1, dtype=torch.int32, device=dev)
+        counts = torch.empty(3 * self.num_buckets, dtype=torch.int32, device=dev)
+        sh_dump(self.handle, None, None, None, counts, count, viol, stream)
+        n = int(count.item())
+        b = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        k = torch.empty_like(b)
+        v = torch.empty_like(b)
+        sh_dump(self.handle, b, k, v, counts, count, viol, stream)
+        torch.cuda.synchronize()
+        b, k, v = to_host_u32(b)[:n], to_host_u32(k)[:n], to_host_u32(v)[:n]
+        order = np.lexsort((k, b))
+        return (b[order], k[order], v[order], to_host_u32(counts).reshape(-1, 3),
+                int(viol.item()))

@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every entry point
+the header declares, sizes storage as documented, and rejects bad arguments before touching a
+device."""
+import ctypes
+import os
+
+import pytest
+
+from paper_1710_11246_amd import slabhash as S
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(S.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return S.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = S.declared_symbols()
+    assert len(declared) >= 13
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(S._SIGS), "binding and header disagree"
+
+
+def test_storage_bytes(lib):
+    p = S.ShParams(4096, 4 * 2048, 12345, 678)
+    want = 256 + 4096 * 256 + 4 * 2048 * 256 + 4 * 256
+    assert S.sh_storage_bytes(p) == want
+    assert S.sh_storage_bytes(S.ShParams(1, 0, 1, 0)) == 256 + 256
+    # invalid: zero buckets, pool not a multiple of 2048, a = 0, a >= p, b >= p
+    for bad in [S.ShParams(0, 0, 1, 0), S.ShParams(8, 100, 1, 0), S.ShParams(8, 0, 0, 0),
+                S.ShParams(8, 0, S.SH_HASH_PRIME, 0), S.ShParams(8, 0, 1, S.SH_HASH_PRIME)]:
+        assert S.sh_storage_bytes(bad) == 0
+
+
+def test_argument_errors_before_any_device_call(lib):
+    p = S.ShParams(16, 0, 3, 5)
+    out = ctypes.c_void_p()
+    # null storage, too small, misaligned, null out: all EINVAL without a device
+    assert lib.sh_create(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(out)) == S.SH_EINVAL
+    assert lib.sh_create(ctypes.byref(p), 256, 16, None, ctypes.byref(out)) == S.SH_EINVAL
+    assert lib.sh_create(ctypes.byref(p), 257, 1 << 20, None, ctypes.byref(out)) == S.SH_EINVAL
+    assert lib.sh_create(ctypes.byref(p), 256, 1 << 20, None, None) == S.SH_EINVAL
+    bad = S.ShParams(0, 0, 1, 0)
+    assert lib.sh_create(ctypes.byref(bad), 256, 1 << 20, None, ctypes.byref(out)) == S.SH_EINVAL
+    # null table handle
+    assert lib.sh_build(None, 256, 256, 10, None, None) == S.SH_EINVAL
+    assert lib.sh_search(None, 256, 10, 256, None, None) == S.SH_EINVAL
+    assert lib.sh_delete(None, 256, 10, None, None) == S.SH_EINVAL
+    assert lib.sh_mixed(None, 256, 256, 256, 10, 256, 256, None) == S.SH_EINVAL
+    assert lib.sh_stats(None, None, None) == S.SH_EINVAL
+    assert lib.sh_dump(None, None, None, None, 0, None, None, None, None) == S.SH_EINVAL
+    assert lib.sh_reset(None, None) == S.SH_EINVAL
+    assert lib.sh_destroy(None) == S.SH_EINVAL
+    assert lib.sh_set_launch(None, None) == S.SH_EINVAL
+
+
+def test_strerror(lib):
+    assert S.sh_strerror(S.SH_OK) == "ok"
+    assert S.sh_strerror(S.SH_EINVAL) == "invalid argument"
+    assert S.sh_strerror(99) == "unknown status"
+
+
+def test_pool_bound_holds_worst_case():
+    # one bucket holding every key needs ceil(n/31) - 1 pool slabs
+    for n in [1, 31, 32, 1000, 2048 * 31 + 5]:
+        assert S.pool_slabs_bound(n, 0) >= -(-n // 31) - 1
+        assert S.pool_slabs_bound(n) % 2048 == 0

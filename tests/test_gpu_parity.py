@@ -1,0 +1,266 @@
+"""GPU parity: the HIP slab hash (through the C ABI) against the CPU oracle on the same seeded
+inputs. Integer results must match bit for bit; concurrent mixed batches must be linearizable
+against the oracle with an identical final table."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1710_11246_amd import slabhash as S
+from paper_1710_11246_amd import workload as W
+
+import linearize as LZ
+
+pytestmark = pytest.mark.gpu
+
+M = S.SH_SLAB_PAIRS
+EMPTY = 0xFFFFFFFF
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    S.lib()
+
+
+def make(oracle_mod, B, a, b, pool):
+    t = S.SlabHash(B, pool, a, b)
+    o = oracle_mod.Oracle(B, M, a, b, pool_slabs=None)
+    return t, o
+
+
+def assert_same_table(t, o, check_counts=True):
+    b, k, v, counts, viol = t.dump()
+    assert viol == 0, "structure invariant violated"
+    ob, ok, ov = o.dump()
+    order = np.lexsort((ok, ob))
+    assert b.size == ob.size
+    assert (b == ob[order]).all() and (k == ok[order]).all() and (v == ov[order]).all()
+    st = t.stats()
+    if check_counts:
+        live, tomb, slabs = o.bucket_stats()
+        assert (counts[:, 0] == live).all()
+        assert (counts[:, 1] == tomb).all()
+        assert (counts[:, 2] == slabs).all()
+        assert st["pool_allocated"] == o.pool_used == int((slabs - 1).sum())
+        assert st["slabs_total"] == o.total_slabs
+    assert st["live"] == ob.size and st["violations"] == 0
+    return st
+
+
+def search_both(t, o, q_np):
+    v, f = t.search(S.to_dev(q_np))
+    ov, of, _ = o.search(q_np)
+    gv, gf = S.to_host_u32(v), f.cpu().numpy()
+    assert (gf == of).all(), "found flags differ"
+    assert (gv == ov).all(), "values differ"
+
+
+def test_config1_phased(oracle_mod):
+    """2^16 keys into 2^12 buckets, 2^16 searches half present, delete 25%, search again."""
+    say("case: config1 seed=1 n=65536 B=4096")
+    wl = W.phased(seed=1, n=1 << 16, n_queries=1 << 16, hit_fraction=0.5,
+                  delete_fraction=0.25, prime=S.SH_HASH_PRIME)
+    B = 1 << 12
+    t, o = make(oracle_mod, B, wl.hash_a, wl.hash_b, S.pool_slabs_bound(1 << 16))
+    st = t.build(S.to_dev(wl["keys"]), S.to_dev(wl["vals"]))
+    assert (st.cpu().numpy() == o.replace(wl["keys"], wl["vals"])).all()
+    search_both(t, o, wl["queries"])
+    ds = t.delete(S.to_dev(wl["deletes"]))
+    assert (ds.cpu().numpy() == o.delete(wl["deletes"])).all()
+    search_both(t, o, wl["queries"])
+    st = assert_same_table(t, o)
+    assert st["error_word"] == 0 and st["tombstones"] == wl["deletes"].size
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 63, 64, 65, 127, 129, 1000, 4097, 20011])
+def test_ragged_sizes(oracle_mod, n):
+    say("case: ragged n=%d B=97" % n)
+    rng = W.SplitMix64(n)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    keys = W.unique_keys(rng, n)
+    vals = W.value_of(keys)
+    miss = W.unique_keys(rng, n, exclude=keys)
+    t, o = make(oracle_mod, 97, a, b, S.pool_slabs_bound(n))
+    st = t.build(S.to_dev(keys), S.to_dev(vals))
+    assert (st.cpu().numpy() == o.replace(keys, vals)).all()
+    search_both(t, o, np.concatenate([keys, miss]))
+    half = keys[: (n + 1) // 2]
+    ds = t.delete(S.to_dev(half))
+    assert (ds.cpu().numpy() == o.delete(half)).all()
+    search_both(t, o, np.concatenate([miss, keys]))
+    # replace existing values (status 2) and re-insert deleted keys (status 1, appended)
+    newv = (vals ^ np.uint32(0x5A5A5A5A)).astype(np.uint32)
+    st = t.insert(S.to_dev(keys), S.to_dev(newv))
+    assert (st.cpu().numpy() == o.replace(keys, newv)).all()
+    search_both(t, o, keys)
+    assert_same_table(t, o)
+
+
+def test_empty_calls_are_noops(oracle_mod):
+    say("case: empty inputs")
+    t, o = make(oracle_mod, 16, 3, 5, 0)
+    e32 = torch.empty(0, dtype=torch.int32, device="cuda")
+    e8 = torch.empty(0, dtype=torch.uint8, device="cuda")
+    S.sh_build(t.handle, e32, e32, e8)
+    S.sh_search(t.handle, e32, e32, e8)
+    S.sh_delete(t.handle, e32, e8)
+    S.sh_mixed(t.handle, e8, e32, e32, e32, e8)
+    st = assert_same_table(t, o)
+    assert st["live"] == 0 and st["slabs_total"] == 16 and st["pool_allocated"] == 0
+
+
+@pytest.mark.parametrize("B,n", [(1, 3000), (4, 20000), (61, 50000)])
+def test_long_chains_and_contention(oracle_mod, B, n):
+    """Few buckets: long slab lists, many wavefronts racing on the same tail slabs."""
+    say("case: contention B=%d n=%d" % (B, n))
+    rng = W.SplitMix64(77 + B)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    keys = W.unique_keys(rng, n)
+    vals = W.value_of(keys)
+    t, o = make(oracle_mod, B, a, b, S.pool_slabs_bound(n))
+    st = t.insert(S.to_dev(keys), S.to_dev(vals))
+    assert (st.cpu().numpy() == o.replace(keys, vals)).all()
+    search_both(t, o, keys[::3])
+    dels = keys[1::4]
+    ds = t.delete(S.to_dev(dels))
+    assert (ds.cpu().numpy() == o.delete(dels)).all()
+    search_both(t, o, keys)
+    assert_same_table(t, o)
+
+
+def test_duplicate_keys_in_one_batch(oracle_mod):
+    """Repeated keys in one insert batch: one insert wins as new (status 1), the rest replace
+    (status 2), and the final value is one of the batch's values for that key."""
+    say("case: duplicates")
+    rng = W.SplitMix64(5)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    base = W.unique_keys(rng, 3000)
+    keys = base[rng.below(20000, base.size)].astype(np.uint32)
+    vals = (rng.next(20000) >> np.uint64(32)).astype(np.uint32)
+    t = S.SlabHash(29, S.pool_slabs_bound(20000), a, b)
+    st = t.insert(S.to_dev(keys), S.to_dev(vals)).cpu().numpy()
+    uk = np.unique(keys)
+    ones = np.bincount(np.searchsorted(uk, keys), weights=(st == 1)).astype(int)
+    assert (ones == 1).all() and ((st == 1) | (st == 2)).all()
+    bb, kk, vv, counts, viol = t.dump()
+    assert viol == 0 and (np.sort(kk) == uk).all()
+    allowed = set(zip(keys.tolist(), vals.tolist()))
+    assert all((k, v) in allowed for k, v in zip(kk.tolist(), vv.tolist()))
+    assert t.stats()["live"] == uk.size
+
+
+def test_reserved_key_flagged(oracle_mod):
+    say("case: reserved key")
+    t, o = make(oracle_mod, 8, 11, 13, S.pool_slabs_bound(100))
+    keys = np.array([1, 2, EMPTY, 3, EMPTY], np.uint32)
+    vals = np.array([10, 20, 30, 40, 50], np.uint32)
+    st = t.insert(S.to_dev(keys), S.to_dev(vals)).cpu().numpy()
+    assert (st == o.replace(keys, vals)).all() and st.tolist() == [1, 1, 0, 1, 0]
+    v, f = t.search(S.to_dev(keys))
+    assert f.cpu().numpy().tolist() == [1, 1, 0, 1, 0]
+    assert S.to_host_u32(v).tolist() == [10, 20, EMPTY, 40, EMPTY]
+    assert t.stats()["error_word"] & S.SH_ERR_RESERVED_KEY
+    assert_same_table(t, o)
+
+
+def test_pool_exhaustion(oracle_mod):
+    """A pool of one block: inserts beyond its capacity fail with status 0 and the error bit;
+    nothing that reported success is lost and nothing that failed is present."""
+    say("case: pool exhaustion")
+    B, pool = 8, 2048
+    rng = W.SplitMix64(31337)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    n = (B + pool) * M + 4000
+    keys = W.unique_keys(rng, n)
+    vals = W.value_of(keys)
+    t = S.SlabHash(B, pool, a, b)
+    st = t.insert(S.to_dev(keys), S.to_dev(vals)).cpu().numpy()
+    assert set(np.unique(st).tolist()) <= {0, 1}
+    assert (st == 0).sum() >= 4000 - B * M
+    s = t.stats()
+    assert s["error_word"] & S.SH_ERR_POOL_EXHAUSTED
+    assert s["pool_allocated"] == pool and s["violations"] == 0
+    v, f = t.search(S.to_dev(keys))
+    f = f.cpu().numpy()
+    assert (f == (st == 1)).all()
+    assert (S.to_host_u32(v)[st == 1] == vals[st == 1]).all()
+    assert s["live"] == int((st == 1).sum())
+
+
+def _grow_and_mix(oracle_mod, n_keys, B, n_batches, batch, seed, gamma=(0.2, 0.2, 0.3, 0.3)):
+    rng = W.SplitMix64(seed)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    keys = W.unique_keys(rng, n_keys)
+    vals = W.value_of(keys)
+    n_ins, n_del, n_hit, n_miss = W.gamma_counts(batch, gamma)
+    fresh = W.unique_keys(rng, n_ins * n_batches + n_miss, exclude=keys)
+    absent = fresh[n_ins * n_batches:]
+    pool = S.pool_slabs_bound(n_keys + n_ins * n_batches)
+    t, o = make(oracle_mod, B, a, b, pool)
+    # incremental growth in batches
+    g = 1 << 16
+    for s in range(0, n_keys, g):
+        st = t.insert(S.to_dev(keys[s:s + g]), S.to_dev(vals[s:s + g]))
+        assert (st.cpu().numpy() == 1).all()
+    o.replace(keys, vals)
+    present = keys.copy()
+    for bi in range(n_batches):
+        ops, bk, bv = W.mixed_batch(rng, present, fresh[bi * n_ins:(bi + 1) * n_ins], absent,
+                                    n_ins, n_del, n_hit, n_miss)
+        pre_v, pre_f, _ = o.search(bk)
+        gv, gs = t.mixed(S.to_dev(ops), S.to_dev(bk), S.to_dev(bv))
+        ov, ost = o.mixed(ops, bk, bv)
+        post_v, post_f, _ = o.search(bk)
+        LZ.check_single_mutation_batch(ops, bk, S.to_host_u32(gv), gs.cpu().numpy(), pre_f,
+                                       pre_v, post_f, post_v, ost)
+        dels = bk[ops == 2]
+        present = np.concatenate([present[~np.isin(present, dels)], bk[ops == 1]])
+    return t, o
+
+
+def test_mixed_batches_linearizable(oracle_mod):
+    say("case: mixed 2^18 keys, 4 batches of 2^16")
+    t, o = _grow_and_mix(oracle_mod, 1 << 18, (1 << 18) // 20, 4, 1 << 16, seed=3)
+    assert_same_table(t, o)
+
+
+def test_mixed_with_repeated_keys_linearizable(oracle_mod):
+    """Many mutations per key in one batch, on a few buckets: the general per-key check."""
+    say("case: mixed repeated keys")
+    rng = W.SplitMix64(12)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    dom = W.unique_keys(rng, 400)
+    t, o = make(oracle_mod, 7, a, b, S.pool_slabs_bound(20000))
+    init = dom[:200]
+    t.insert(S.to_dev(init), S.to_dev(W.value_of(init)))
+    o.replace(init, W.value_of(init))
+    for it in range(3):
+        n = 2000
+        ops = rng.below(n, 3).astype(np.uint8)
+        keys = dom[rng.below(n, dom.size)].astype(np.uint32)
+        # at most 6 mutations of any key, so the brute-force order search stays small
+        mut_keys = keys[ops != 0]
+        uk, cnt = np.unique(mut_keys, return_counts=True)
+        over = np.isin(keys, uk[cnt > 6]) & (ops != 0)
+        ops[over] = 0
+        vals = (rng.next(n) >> np.uint64(32)).astype(np.uint32)
+        _, ok_, ov_ = o.dump()
+        pre = LZ.state_lookup(ok_, ov_)
+        gv, gs = t.mixed(S.to_dev(ops), S.to_dev(keys), S.to_dev(vals))
+        tb, tk, tv, _, viol = t.dump()
+        assert viol == 0
+        post = LZ.state_lookup(tk, tv)
+        LZ.check_batch(ops, keys, vals, S.to_host_u32(gv), gs.cpu().numpy(), pre, post)
+        # keys not in the batch keep their state
+        untouched = np.setdiff1d(ok_, keys)
+        assert all(post(int(k)) == pre(int(k)) for k in untouched)
+        # continue from the GPU's state: rebuild the oracle from its dump
+        o = oracle_mod.Oracle(7, M, a, b)
+        o.replace(tk, tv)
