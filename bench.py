@@ -171,7 +171,9 @@ def main():
     avg_ms = {k: (sum(a.elapsed_time(b) for a, b in v) / len(v)) for k, v in ev.items()}
     per_step_ms = {k: avg_ms[k] * (MIX_BATCHES if k == "mixed" else 1) for k in avg_ms}
 
-    # Structure of the built table (before the mixed batches) for the byte accounting.
+    # Structure of the built table (before the mixed batches) for the byte accounting, with
+    # the operation counters switched on for this one build.
+    S.sh_set_launch(h, args.waves_per_cu, 0, S.SH_LAUNCH_COUNTERS)
     S.sh_reset(h, stream)
     S.sh_build(h, keys, vals, st_build, stream)
     assert bool((st_build == 1).all())
@@ -182,6 +184,10 @@ def main():
     v_hit = chain_visits(occ) / N_KEYS
     v_miss = float(counts[:, 2].mean())
     new_slabs = stats_built["pool_allocated"]
+    build_counters = {k: stats_built[k] for k in
+                      ("rounds", "cas_lost", "allocs", "link_lost", "block_moves")}
+    build_counters["rounds_per_chunk"] = round(stats_built["rounds"] / (N_KEYS / 64), 4)
+    S.sh_set_launch(h, args.waves_per_cu, 0, 0)
     util = 8.0 * stats_built["live"] / (256.0 * stats_built["slabs_total"])
 
     # Algorithmic bytes per launch ("Roofline and algorithmic bytes").
@@ -264,6 +270,7 @@ def main():
             "slabs_per_miss": round(v_miss, 4),
         },
         "kernels": kernels,
+        "build_counters": build_counters,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -68,11 +68,19 @@ typedef struct {
     uint32_t hash_b;      /* 0 <= b < p */
 } sh_params_t;
 
-/* Launch shape of the operation kernels: persistent grid of waves_per_cu * (compute units)
-   wavefronts (0 = library default). Never changes results. */
+/* Launch shape of the operation kernels. Never changes results.
+   waves_per_cu: persistent grid of waves_per_cu * (compute units) wavefronts, at most 64
+                 (0 = library default, 16).
+   ops_per_wave: operations each wavefront holds at a time, one per lane: 8, 16, 32 or 64
+                 (0 = chosen per call: 64, halved while the batch would not fill the grid).
+   flags:        SH_LAUNCH_COUNTERS makes the operation kernels accumulate the counters that
+                 sh_stats reports (off by default: it adds atomics at the end of each kernel). */
+enum { SH_LAUNCH_COUNTERS = 1u };
 typedef struct {
     uint32_t waves_per_cu;
-    uint32_t reserved[3];
+    uint32_t ops_per_wave;
+    uint32_t flags;
+    uint32_t reserved;
 } sh_launch_t;
 
 typedef struct sh_table sh_table_t; /* opaque host handle */
@@ -86,10 +94,15 @@ typedef struct {
     uint32_t error_word;     /* SH_ERR_* bits raised since create/reset */
     uint32_t violations;     /* structure-invariant violations seen by the walk (0 expected) */
     uint32_t num_buckets, hash_a, hash_b, hash_p;
+    /* Operation counters since create/reset, summed over wavefronts, accumulated only while
+       SH_LAUNCH_COUNTERS is set: decision rounds (one per chunk of ops and pass over it), swaps
+       lost to another wavefront, slabs allocated, links lost (slab freed again), allocator
+       moves to another block. */
+    uint64_t rounds, cas_lost, allocs, link_lost, block_moves;
 } sh_stats_t;
 
 /* Device bytes a table with these parameters needs (header + base slabs + pool + bitmaps).
-   Returns 0 for invalid parameters. */
+   Returns 0 for invalid parameters (including num_buckets + pool_slabs >= 2^32 - 1). */
 size_t sh_storage_bytes(const sh_params_t *p);
 
 /* Bind a table to caller-owned device storage (256-byte aligned, at least sh_storage_bytes)
@@ -104,7 +117,8 @@ sh_status_t sh_reset(sh_table_t *t, void *stream);
 /* Free the host handle only; the device storage stays the caller's. */
 sh_status_t sh_destroy(sh_table_t *t);
 
-/* Set the launch shape used by later calls on this table (NULL restores the default). */
+/* Set the launch shape used by later calls on this table (NULL restores the default).
+   Out-of-range fields give SH_EINVAL. */
 sh_status_t sh_set_launch(sh_table_t *t, const sh_launch_t *shape);
 
 /* Bulk build: insert n pairs, each lane of a wavefront holding one ("Bulk benchmarks"; the

@@ -14,16 +14,10 @@
 // lanes 32..63 either mirror them or hold a second slab. Each slot is therefore read whole, so a
 // reader never sees a key from one write and a value from another.
 //
-// Work sharing ("Our warp-cooperative work sharing strategy"): every lane holds one operation,
-// and the whole wavefront processes the queued operations one at a time in lane order, with
-// ballots and lane reads. Per chunk of 64 operations the kernel runs
-//   pass 1: the base slabs of all 64 operations are loaded up front (32 two-slab loads), then
-//           each operation is decided on its base slab in lane order. Searches and deletes that
-//           resolve there finish; inserts and deletes that resolve there record a compare-and-
-//           swap, and the chunk's swaps are issued together as one vector atomic.
-//   pass 2: every operation not finished by pass 1 (chain continues, swap lost, new slab
-//           needed) goes through the paper's loop (Fig. "Pseudocode for search, insert and
-//           delete"): read slab, ballot, swap or follow the next index, allocate at the tail.
+// Work sharing ("Our warp-cooperative work sharing strategy"): every lane holds one operation
+// and the whole wavefront decides the queued operations one at a time in lane order, with
+// ballots and lane reads; the slab loads for all of a chunk's operations are issued ahead of the
+// decisions and the resulting swaps are committed together (see ops_kernel).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -40,7 +34,9 @@ constexpr uint64_t kSlotMask = 0x7FFFFFFFull;         // slots 0..30 of a half w
 constexpr uint32_t kPrime = SH_HASH_PRIME;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr size_t kHeaderBytes = 256;
+constexpr size_t kHeaderBytes = 4096;   // Header, then the counter slots
+constexpr uint32_t kCounterSlots = 32;   // 64-byte slots of 8 counters, one per wavefront % 32
+constexpr uint32_t kFlagCounters = SH_LAUNCH_COUNTERS;
 constexpr uint32_t kDefaultWavesPerCU = 16;
 
 enum Kind { kSearch = 0, kInsert = 1, kDelete = 2, kMixed = 3 };
@@ -56,6 +52,7 @@ struct View {
     uint64_t *pool;   // P slabs of 32 words
     uint32_t *bitmap; // P/2048 rows of 64 words
     Header *hdr;
+    unsigned long long *counters; // kCounterSlots x 8
     uint32_t B, a, b, pool_slabs, nblk;
 };
 
@@ -73,11 +70,19 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ uint32_t ffs0(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
 
-// Give lane `j` the wave-uniform value v, leaving other lanes' x unchanged.
-__device__ __forceinline__ void put(uint32_t &x, uint32_t lane, uint32_t j, uint32_t v)
+// v_writelane_b32: lane `j` of x takes the wave-uniform value v (bound to the LLVM intrinsic so
+// the compiler still schedules and checks hazards around it).
+extern "C" __device__ uint32_t sh_llvm_writelane(uint32_t v, uint32_t j, uint32_t x)
+    __asm("llvm.amdgcn.writelane.i32");
+
+__device__ __forceinline__ uint32_t wl(uint32_t x, uint32_t j, uint32_t v)
 {
-    x = (lane == j) ? v : x;
+    return sh_llvm_writelane(v, j, x);
 }
+
+// s_waitcnt vmcnt(0): wait for every outstanding vector memory access of this wavefront
+// (gfx9 encoding: vmcnt 0, expcnt 7, lgkmcnt 15 left unconstrained).
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Universal hash of the "Slab Hash" subsection: ((a k + b) mod p) mod B with p = 2^32 - 5.
 // a k + b < 2^64; since 2^32 = 5 (mod p) two folds of the high half bring it below 2^32 + 30,
@@ -119,16 +124,6 @@ __device__ __forceinline__ uint32_t cas32(uint32_t *p, uint32_t expected, uint32
     return expected;
 }
 
-// One lane (`who`) performs the swap; every lane gets the old value.
-__device__ __forceinline__ uint64_t cas64_by(uint64_t *p, uint64_t expected, uint64_t desired,
-                                             uint32_t lane, uint32_t who)
-{
-    uint64_t old = 0;
-    if (lane == who)
-        old = cas64(p, expected, desired);
-    return ((uint64_t)rl((uint32_t)(old >> 32), who) << 32) | rl((uint32_t)old, who);
-}
-
 __device__ __forceinline__ void raise_error(const View &T, uint32_t bits, uint32_t lane,
                                             uint32_t who)
 {
@@ -160,6 +155,7 @@ struct Alloc {
     uint32_t blk;   // resident block (wave-uniform), kEmpty = none yet
     uint32_t word;  // this lane's bitmap word of the resident block
     uint32_t moves; // block moves since the last successful allocation
+    uint32_t total_moves;
     uint32_t start; // first block tried
     bool full;      // this wavefront found the pool exhausted
 };
@@ -199,6 +195,7 @@ __device__ uint32_t wave_alloc(const View &T, Alloc &s, uint32_t lane)
             s.full = true;
             return kEmpty;
         }
+        ++s.total_moves;
         s.blk = (s.blk + 1 == T.nblk) ? 0 : s.blk + 1;
         s.word = load_word_coherent(&T.bitmap[(size_t)s.blk * 64 + lane]);
     }
@@ -211,120 +208,82 @@ __device__ __forceinline__ void slab_free(const View &T, uint32_t idx)
 }
 
 // ---------------------------------------------------------------------------------------------
-// The per-operation loop (pass 2). One queued operation at a time: the source lane's key is
-// broadcast, the wavefront reads the current slab, votes for the key (and for empty slots when
-// inserting), and either finishes, swaps, follows the next index, or allocates and links a new
-// tail slab. `start` is kEmpty to begin at the base slab, else a pool slab index to resume at.
+// Operation kernel. Persistent grid: wavefront w takes chunks w, w + W, w + 2W, ... of C ops
+// (C = ops per wavefront, 8..64), lane l < C holding op l of its chunk. Each op keeps a cursor
+// `loc` (kEmpty = its bucket's base slab, else a pool slab index). The pool directly follows the
+// base slabs in memory, so slab (loc == kEmpty ? bucket : B + loc) of the base array addresses
+// either. A chunk is processed in rounds until every op has finished:
+//   1. load: the cursor slab of every unfinished op is read, two ops per load instruction
+//      (lanes 0..31 read op 2q's slab, lanes 32..63 op 2q+1's), all loads issued up front in one
+//      straight run (a pair with no unfinished op reads slab 0).
+//   2. decide: the ops are taken in lane order, a pair per step. The wavefront votes on each
+//      slab for the op's key (and, for inserts, for empty slots). Exactly one lane of each half
+//      is the op's target: the slot holding the key, else (inserts) the first empty slot, else
+//      slot 31, which holds the next-slab index. The target lane writes the op's outcome to the
+//      op's cell in LDS: found (with the value), a swap to record (insert into the empty slot,
+//      replace the key's value, tombstone the key; with the observed value), move on to the
+//      next slab (with its index), end of list, or a new slab needed.
+//   3. each op reads its cell: searches finish or move; updates record their swap; the swaps
+//      are issued together as one vector atomic. An insert that loses its empty slot learns the
+//      slot's new occupant from the swap: the same key turns it into a replace of that slot,
+//      another key sends it to the following slot at once. Slots fill in order, so this walk
+//      sees every slot filled since the slab was read. Any other lost swap keeps its op and
+//      cursor, and the next round re-reads that slab;
+//   4. allocate: ops at a full tail slab are served one at a time: SlabAlloc gives a slab, lane 0
+//      links it with a swap on the tail's next index (a lost link frees the slab and follows
+//      the winner's), and the op's cursor moves to the linked slab.
+// With kFlagCounters, per-wavefront counts of rounds, lost swaps, allocations, lost links and
+// allocator block moves are added at the end to one of kCounterSlots header slots.
 
-template <bool Coherent>
-__device__ void wave_op(const View &T, Alloc &al, uint32_t lane, uint32_t op, uint32_t k,
-                        uint32_t v, uint32_t bkt, uint32_t start, uint32_t &res_v,
-                        uint32_t &res_s)
-{
-    const uint32_t slot = lane & 31;
-    uint64_t *cur = (start == kEmpty) ? T.base + (size_t)bkt * 32 : T.pool + (size_t)start * 32;
-    res_v = kEmpty;
-    res_s = 0;
-    for (;;) {
-        const uint64_t w = load_slot<Coherent>(cur + slot);
-        const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-        const uint64_t match = ballot(lo == k) & kSlotMask;
-        const uint32_t next = rl(hi, 31);
-        if (op == kSearch) {
-            if (match) {
-                res_v = rl(hi, ffs0(match));
-                res_s = 1;
-                return;
-            }
-        } else if (op == kDelete) {
-            if (match) {
-                const uint32_t d = ffs0(match);
-                const uint64_t expect = ((uint64_t)rl(hi, d) << 32) | k;
-                if (cas64_by(cur + d, expect, kTombPair, lane, 0) == expect) {
-                    res_s = 1;
-                    return;
-                }
-                continue; // the slot changed under us: read the same slab again
-            }
-        } else {
-            uint32_t d = 32, st = 0;
-            uint64_t expect = kEmptyPair;
-            if (match) {
-                d = ffs0(match);
-                expect = ((uint64_t)rl(hi, d) << 32) | k;
-                st = 2;
-            } else {
-                const uint64_t empty = ballot(w == kEmptyPair) & kSlotMask;
-                if (empty) {
-                    d = ffs0(empty);
-                    st = 1;
-                }
-            }
-            if (d < 32) {
-                const uint64_t desired = ((uint64_t)v << 32) | k;
-                if (cas64_by(cur + d, expect, desired, lane, 0) == expect) {
-                    res_s = st;
-                    return;
-                }
-                continue;
-            }
-            if (next == kEmpty) {
-                // Tail slab is full: allocate, then link with a swap on the next index.
-                const uint32_t idx = wave_alloc(T, al, lane);
-                if (idx == kEmpty) {
-                    raise_error(T, SH_ERR_POOL_EXHAUSTED, lane, 0);
-                    return;
-                }
-                uint32_t *link = reinterpret_cast<uint32_t *>(cur + 31) + 1;
-                uint32_t old = 0;
-                if (lane == 0)
-                    old = cas32(link, kEmpty, idx);
-                old = rl(old, 0);
-                if (old == kEmpty) {
-                    cur = T.pool + (size_t)idx * 32;
-                } else {
-                    if (lane == 0)
-                        slab_free(T, idx); // another wavefront linked first
-                    cur = T.pool + (size_t)old * 32;
-                }
-                continue;
-            }
-        }
-        if (next == kEmpty)
-            return; // end of the list: not found / nothing to delete
-        cur = T.pool + (size_t)next * 32;
-    }
-}
+struct Counters {
+    uint32_t rounds, cas_lost, allocs, link_lost;
+};
 
-// ---------------------------------------------------------------------------------------------
-// Operation kernel. Persistent grid: wavefront w takes chunks w, w + W, w + 2W, ... of 64 ops.
+// Outcome codes written by a target lane (bits 8.. of the message's high word; bits 0..7 hold
+// the target slot).
+enum : uint32_t { kMsgFound = 1, kMsgEnd = 2, kMsgMove = 3, kMsgGrow = 4, kMsgSwapIns = 5,
+                  kMsgSwapRep = 6, kMsgSwapDel = 7 };
 
 template <int K>
 __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__restrict__ ops,
                                                      const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ vals,
                                                      uint64_t n, uint32_t *__restrict__ vout,
-                                                     uint8_t *__restrict__ sout, uint32_t seq)
+                                                     uint8_t *__restrict__ sout, uint32_t seq,
+                                                     uint32_t C, uint32_t flags)
 {
     constexpr bool kCoherent = (K != kSearch);
+    constexpr bool kHasIns = (K == kInsert || K == kMixed);
+    // Per wavefront: cursor slab index, key and op kind of each op, and each op's outcome cell.
+    __shared__ uint32_t s_u[kWavesPerBlock][64];
+    __shared__ uint32_t s_key[kWavesPerBlock][64];
+    __shared__ uint32_t s_op[kWavesPerBlock][64];
+    __shared__ uint64_t s_msg[kWavesPerBlock][64];
+    const uint32_t wl_ = threadIdx.x >> 6;
     const uint32_t lane = lane_id();
     const uint32_t half = lane >> 5, slot = lane & 31;
-    const uint32_t wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const bool is31 = slot == 31;
+    const uint32_t below = (1u << slot) - 1u; // slots of my half below mine
+    const uint32_t hshift = lane & 32;
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + wl_;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const uint64_t *lane_base = T.base + slot; // this lane's slot of slab 0
     Alloc al;
     al.blk = kEmpty;
     al.word = 0;
     al.moves = 0;
+    al.total_moves = 0;
     al.full = false;
     al.start = mix32(wave * 0x9E3779B9u + seq);
+    Counters cnt = {0, 0, 0, 0};
 
-    const uint64_t nchunks = (n + 63) >> 6;
+    const uint64_t nchunks = (n + C - 1) / C;
     for (uint64_t c = wave; c < nchunks; c += nwaves) {
-        const uint64_t i = (c << 6) + lane;
-        const bool in = i < n;
+        const uint64_t i = c * C + lane;
+        const bool in = lane < C && i < n;
         const uint32_t key = in ? keys[i] : kEmpty;
         uint32_t val = 0;
-        if constexpr (K == kInsert || K == kMixed)
+        if constexpr (kHasIns)
             val = in ? vals[i] : 0;
         uint32_t op = (uint32_t)K;
         if constexpr (K == kMixed)
@@ -335,101 +294,158 @@ __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__re
             raise_error(T, SH_ERR_RESERVED_KEY, lane, ffs0(res_m));
         const bool act = in && !reserved && op <= 2;
         const uint32_t bkt = act ? bucket_of(key, T.a, T.b, T.B) : 0u;
-        const uint64_t act_m = ballot(act);
+        s_key[wl_][lane] = key;
+        if constexpr (K == kMixed)
+            s_op[wl_][lane] = op;
 
         uint32_t rv = kEmpty, rs = 0; // this lane's results
-        uint64_t pend = 0;            // ops left for pass 2
-        uint32_t pnext = kEmpty;      // where pass 2 resumes (kEmpty = base slab)
-        uint32_t cmode = 0, cslot = 0, cvobs = 0; // recorded swap: 1 insert, 2 replace, 3 delete
-
-        // ---- pass 1: prefetch all 64 base slabs, two per load instruction ----
-        uint64_t pre[32];
+        uint32_t loc = kEmpty;        // this lane's cursor
+        uint64_t todo = ballot(act);
+        while (todo) {
+            ++cnt.rounds;
+            // ---- 1. load ----
+            s_u[wl_][lane] = ((todo >> lane) & 1) ? ((loc == kEmpty) ? bkt : T.B + loc) : 0u;
+            __builtin_amdgcn_wave_barrier();
+            uint64_t pre[32];
 #pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            const uint32_t b0 = rl(bkt, 2 * q), b1 = rl(bkt, 2 * q + 1);
-            const uint32_t bs = half ? b1 : b0;
-            pre[q] = load_slot<kCoherent>(T.base + (size_t)bs * 32 + slot);
-        }
+            for (int q = 0; q < 32; ++q) {
+                const uint32_t u = s_u[wl_][2 * q + half];
+                pre[q] = load_slot<kCoherent>(lane_base + (size_t)u * 32);
+            }
+            // ---- 2. decide: the target lane of each op writes the op's outcome ----
 #pragma unroll
-        for (int j = 0; j < 64; ++j) {
-            if (!((act_m >> j) & 1))
-                continue;
-            const int h = (j & 1) * 32;
-            const uint32_t lo = (uint32_t)pre[j >> 1], hi = (uint32_t)(pre[j >> 1] >> 32);
-            const uint32_t kj = rl(key, j);
-            const uint32_t oj = (K == kMixed) ? rl(op, j) : (uint32_t)K;
-            const uint64_t match = (ballot(lo == kj) >> h) & kSlotMask;
-            if (oj == kSearch) {
-                if (match) {
-                    put(rv, lane, j, rl(hi, ffs0(match) + h));
-                    put(rs, lane, j, 1);
-                } else {
-                    const uint32_t nx = rl(hi, 31 + h);
-                    if (nx != kEmpty) {
-                        pend |= 1ull << j;
-                        put(pnext, lane, j, nx);
-                    }
+            for (int q = 0; q < 32; ++q) {
+                if (!((todo >> (2 * q)) & 3ull))
+                    continue;
+                const uint64_t w = pre[q];
+                const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+                const uint32_t kq = s_key[wl_][2 * q + half];
+                const bool is_key = !is31 && lo == kq;
+                const uint32_t kh = (uint32_t)(ballot(is_key) >> hshift); // my half's key votes
+                bool ins = (K == kInsert);
+                uint32_t code_key = (K == kSearch) ? kMsgFound
+                                                   : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
+                if constexpr (K == kMixed) {
+                    const uint32_t oq = s_op[wl_][2 * q + half];
+                    ins = oq == kInsert;
+                    code_key = (oq == kSearch) ? kMsgFound
+                                               : ((oq == kDelete) ? kMsgSwapDel : kMsgSwapRep);
                 }
-            } else if (oj == kDelete) {
-                if (match) {
-                    const uint32_t d = ffs0(match);
-                    put(cmode, lane, j, 3);
-                    put(cslot, lane, j, d);
-                    put(cvobs, lane, j, rl(hi, d + h));
+                bool target;
+                uint32_t code;
+                if constexpr (kHasIns) {
+                    const bool is_empty = !is31 && w == kEmptyPair;
+                    const uint32_t eh = (uint32_t)(ballot(is_empty) >> hshift);
+                    const bool first_empty = ins && is_empty && (eh & below) == 0u;
+                    const bool tail = is31 && (!ins || eh == 0u);
+                    target = is_key || (kh == 0u && (first_empty || tail));
+                    code = is_key ? code_key
+                                  : (first_empty ? kMsgSwapIns
+                                                 : (hi != kEmpty ? kMsgMove
+                                                                 : (ins ? kMsgGrow : kMsgEnd)));
                 } else {
-                    const uint32_t nx = rl(hi, 31 + h);
-                    if (nx != kEmpty) {
-                        pend |= 1ull << j;
-                        put(pnext, lane, j, nx);
-                    }
+                    target = is_key || (kh == 0u && is31);
+                    code = is_key ? code_key : (hi != kEmpty ? kMsgMove : kMsgEnd);
                 }
-            } else {
-                if (match) {
-                    const uint32_t d = ffs0(match);
-                    put(cmode, lane, j, 2);
-                    put(cslot, lane, j, d);
-                    put(cvobs, lane, j, rl(hi, d + h));
-                } else {
-                    const uint64_t empty = (ballot(pre[j >> 1] == kEmptyPair) >> h) & kSlotMask;
-                    if (empty) {
-                        put(cmode, lane, j, 1);
-                        put(cslot, lane, j, ffs0(empty));
+                if (target)
+                    s_msg[wl_][2 * q + half] = ((uint64_t)((code << 8) | slot) << 32) | hi;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // ---- 3. act on the outcome ----
+            const bool mine = (todo >> lane) & 1;
+            const uint64_t msg = mine ? s_msg[wl_][lane] : 0ull;
+            const uint32_t payload = (uint32_t)msg;
+            const uint32_t code = mine ? (uint32_t)(msg >> 40) : 0u;
+            const uint32_t tslot = (uint32_t)(msg >> 32) & 255u;
+            if (code == kMsgFound) {
+                rv = payload;
+                rs = 1;
+            }
+            if (code == kMsgMove)
+                loc = payload;
+            bool done = code == kMsgFound || code == kMsgEnd;
+            uint64_t alloc_m = 0;
+            if constexpr (K != kSearch) {
+                bool won = false, lost = false;
+                if (code >= kMsgSwapIns) {
+                    uint32_t cslot = tslot;
+                    uint64_t *slab = T.base + (size_t)((loc == kEmpty) ? bkt : T.B + loc) * 32;
+                    const uint64_t desired =
+                        (code == kMsgSwapDel) ? kTombPair : (((uint64_t)val << 32) | key);
+                    uint64_t expect = (code == kMsgSwapIns) ? kEmptyPair
+                                                            : (((uint64_t)payload << 32) | key);
+                    uint64_t old = cas64(slab + cslot, expect, desired);
+                    if (old == expect) {
+                        rs = (code == kMsgSwapRep) ? 2u : 1u;
+                        won = true;
+                    } else if (code == kMsgSwapIns) {
+                        // Walk forward from the lost empty slot using the occupants the swaps
+                        // return; at most the 31 slots of this slab.
+                        for (;;) {
+                            if ((uint32_t)old == key) { // the same key was inserted: replace it
+                                expect = old;
+                                old = cas64(slab + cslot, expect, desired);
+                                if (old == expect) {
+                                    rs = 2u;
+                                    won = true;
+                                } else {
+                                    lost = true;
+                                }
+                                break;
+                            }
+                            if (++cslot >= 31) {
+                                lost = true; // slab filled up: the next round follows `next`
+                                break;
+                            }
+                            old = cas64(slab + cslot, kEmptyPair, desired);
+                            if (old == kEmptyPair) {
+                                rs = 1u;
+                                won = true;
+                                break;
+                            }
+                        }
                     } else {
-                        // Base slab full: continue down the chain, or allocate at the base.
-                        pend |= 1ull << j;
-                        put(pnext, lane, j, rl(hi, 31 + h));
+                        lost = true;
+                    }
+                }
+                done = done || won;
+                if (flags & kFlagCounters)
+                    cnt.cas_lost += (uint32_t)__popcll(ballot(lost));
+                alloc_m = ballot(code == kMsgGrow);
+            }
+            todo &= ~ballot(done);
+            if constexpr (K != kSearch) {
+                // ---- 4. allocate and link new tail slabs, one op at a time ----
+                while (alloc_m) {
+                    const uint32_t j = ffs0(alloc_m);
+                    alloc_m &= alloc_m - 1;
+                    const uint32_t lj = rl(loc, j), bj = rl(bkt, j);
+                    uint64_t *tail = T.base + (size_t)((lj == kEmpty) ? bj : T.B + lj) * 32;
+                    const uint32_t idx = wave_alloc(T, al, lane);
+                    if (idx == kEmpty) {
+                        raise_error(T, SH_ERR_POOL_EXHAUSTED, lane, 0);
+                        todo &= ~(1ull << j); // status stays 0
+                        continue;
+                    }
+                    ++cnt.allocs;
+                    uint32_t *link = reinterpret_cast<uint32_t *>(tail + 31) + 1;
+                    uint32_t old = 0;
+                    if (lane == 0)
+                        old = cas32(link, kEmpty, idx);
+                    old = rl(old, 0);
+                    if (old == kEmpty) {
+                        loc = wl(loc, j, idx);
+                    } else {
+                        ++cnt.link_lost;
+                        if (lane == 0)
+                            slab_free(T, idx); // another wavefront linked first
+                        loc = wl(loc, j, old);
                     }
                 }
             }
-        }
-        if constexpr (K != kSearch) {
-            // Commit the recorded swaps of the chunk together; losers redo the op in pass 2.
-            bool lost = false;
-            if (cmode) {
-                uint64_t *sp = T.base + (size_t)bkt * 32 + cslot;
-                const uint64_t expect =
-                    (cmode == 1) ? kEmptyPair : (((uint64_t)cvobs << 32) | key);
-                const uint64_t desired = (cmode == 3) ? kTombPair : (((uint64_t)val << 32) | key);
-                if (cas64(sp, expect, desired) == expect)
-                    rs = (cmode == 2) ? 2u : 1u;
-                else
-                    lost = true;
-            }
-            const uint64_t lost_m = ballot(lost);
-            pend |= lost_m;
-            if (lost)
-                pnext = kEmpty;
-        }
-
-        // ---- pass 2: the remaining ops, one at a time in lane order ----
-        while (pend) {
-            const uint32_t j = ffs0(pend);
-            pend &= pend - 1;
-            uint32_t ov, os;
-            wave_op<kCoherent>(T, al, lane, (K == kMixed) ? rl(op, j) : (uint32_t)K, rl(key, j),
-                               rl(val, j), rl(bkt, j), rl(pnext, j), ov, os);
-            put(rv, lane, j, ov);
-            put(rs, lane, j, os);
+            // Every load of this round has been consumed; saying so lets the compiler issue the
+            // next round's loads back to back instead of waiting before each one.
+            wait_vm_all();
         }
 
         if (in) {
@@ -438,6 +454,14 @@ __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__re
             if (sout)
                 sout[i] = (uint8_t)rs;
         }
+    }
+    if ((flags & kFlagCounters) && lane == 0) {
+        unsigned long long *cs = T.counters + (size_t)(wave % kCounterSlots) * 8;
+        atomicAdd(cs + 0, (unsigned long long)cnt.rounds);
+        atomicAdd(cs + 1, (unsigned long long)cnt.cas_lost);
+        atomicAdd(cs + 2, (unsigned long long)cnt.allocs);
+        atomicAdd(cs + 3, (unsigned long long)cnt.link_lost);
+        atomicAdd(cs + 4, (unsigned long long)al.total_moves);
     }
 }
 
@@ -584,6 +608,8 @@ struct sh_table {
     View v;
     uint32_t seq;
     uint32_t waves_per_cu;
+    uint32_t ops_per_wave; // 0 = chosen per call
+    uint32_t flags;        // SH_LAUNCH_* bits
     int num_cu;
 };
 
@@ -596,7 +622,8 @@ struct Layout {
 bool layout_of(const sh_params_t *p, Layout *L)
 {
     if (!p || p->num_buckets == 0 || p->pool_slabs % SH_BLOCK_SLABS != 0 || p->hash_a == 0 ||
-        p->hash_a >= kPrime || p->hash_b >= kPrime)
+        p->hash_a >= kPrime || p->hash_b >= kPrime ||
+        (uint64_t)p->num_buckets + p->pool_slabs >= 0xFFFFFFFFull)
         return false;
     L->base = kHeaderBytes;
     L->pool = L->base + (size_t)p->num_buckets * SH_SLAB_BYTES;
@@ -612,9 +639,22 @@ sh_status_t check_launch()
     return hipGetLastError() == hipSuccess ? SH_OK : SH_EHIP;
 }
 
-uint32_t grid_for(const sh_table *t, uint64_t n)
+// Ops per wavefront: 64 (one per lane) unless that leaves fewer chunks than half the persistent
+// grid's wavefronts, then halved down to 8 so small batches still spread over the chip.
+uint32_t ops_per_wave_for(const sh_table *t, uint64_t n)
 {
-    const uint64_t chunks = (n + 63) / 64;
+    if (t->ops_per_wave)
+        return t->ops_per_wave;
+    const uint64_t waves = (uint64_t)t->num_cu * t->waves_per_cu;
+    uint32_t C = 64;
+    while (C > 8 && 2 * ((n + C - 1) / C) < waves)
+        C >>= 1;
+    return C;
+}
+
+uint32_t grid_for(const sh_table *t, uint64_t n, uint32_t C)
+{
+    const uint64_t chunks = (n + C - 1) / C;
     uint64_t waves = (uint64_t)t->num_cu * t->waves_per_cu;
     if (waves > chunks)
         waves = chunks;
@@ -651,8 +691,9 @@ sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
         return SH_OK;
     if (n >= (1ull << 32) || !keys)
         return SH_EINVAL;
-    hipLaunchKernelGGL(ops_kernel<K>, dim3(grid_for(t, n)), dim3(kBlock), 0, S(stream), t->v,
-                       ops, keys, vals, n, vout, sout, t->seq++);
+    const uint32_t C = ops_per_wave_for(t, n);
+    hipLaunchKernelGGL(ops_kernel<K>, dim3(grid_for(t, n, C)), dim3(kBlock), 0, S(stream), t->v,
+                       ops, keys, vals, n, vout, sout, t->seq++, C, t->flags);
     return check_launch();
 }
 
@@ -719,6 +760,7 @@ sh_status_t sh_create(const sh_params_t *p, void *d_storage, size_t bytes, void 
     t->waves_per_cu = kDefaultWavesPerCU;
     t->seq = 0;
     t->v.hdr = reinterpret_cast<Header *>(t->storage);
+    t->v.counters = reinterpret_cast<unsigned long long *>(t->storage + 256);
     t->v.base = reinterpret_cast<uint64_t *>(t->storage + L.base);
     t->v.pool = reinterpret_cast<uint64_t *>(t->storage + L.pool);
     t->v.bitmap = reinterpret_cast<uint32_t *>(t->storage + L.bitmap);
@@ -755,13 +797,19 @@ sh_status_t sh_set_launch(sh_table_t *t, const sh_launch_t *shape)
 {
     if (!t)
         return SH_EINVAL;
-    if (!shape || shape->waves_per_cu == 0) {
+    if (!shape) {
         t->waves_per_cu = kDefaultWavesPerCU;
+        t->ops_per_wave = 0;
+        t->flags = 0;
         return SH_OK;
     }
-    if (shape->waves_per_cu > 64)
+    const uint32_t c = shape->ops_per_wave;
+    if (shape->waves_per_cu > 64 || (c != 0 && c != 8 && c != 16 && c != 32 && c != 64) ||
+        (shape->flags & ~(uint32_t)SH_LAUNCH_COUNTERS))
         return SH_EINVAL;
-    t->waves_per_cu = shape->waves_per_cu;
+    t->waves_per_cu = shape->waves_per_cu ? shape->waves_per_cu : kDefaultWavesPerCU;
+    t->ops_per_wave = c;
+    t->flags = shape->flags;
     return SH_OK;
 }
 
@@ -810,10 +858,17 @@ sh_status_t sh_stats(sh_table_t *t, sh_stats_t *h_out, void *stream)
     if (s != SH_OK)
         return s;
     Header h;
+    unsigned long long cs[kCounterSlots * 8];
     if (hipMemcpyAsync(&h, t->v.hdr, sizeof(Header), hipMemcpyDeviceToHost, S(stream)) !=
+            hipSuccess ||
+        hipMemcpyAsync(cs, t->v.counters, sizeof(cs), hipMemcpyDeviceToHost, S(stream)) !=
             hipSuccess ||
         hipStreamSynchronize(S(stream)) != hipSuccess)
         return SH_EHIP;
+    unsigned long long sum[5] = {0, 0, 0, 0, 0};
+    for (uint32_t k = 0; k < kCounterSlots; ++k)
+        for (int f = 0; f < 5; ++f)
+            sum[f] += cs[k * 8 + f];
     memset(h_out, 0, sizeof(*h_out));
     h_out->live = h.live;
     h_out->tombstones = h.tomb;
@@ -826,6 +881,11 @@ sh_status_t sh_stats(sh_table_t *t, sh_stats_t *h_out, void *stream)
     h_out->hash_a = t->p.hash_a;
     h_out->hash_b = t->p.hash_b;
     h_out->hash_p = kPrime;
+    h_out->rounds = sum[0];
+    h_out->cas_lost = sum[1];
+    h_out->allocs = sum[2];
+    h_out->link_lost = sum[3];
+    h_out->block_moves = sum[4];
     return SH_OK;
 }
 

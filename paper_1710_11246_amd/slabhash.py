@@ -36,8 +36,12 @@ class ShParams(ctypes.Structure):
                 ("hash_a", ctypes.c_uint32), ("hash_b", ctypes.c_uint32)]
 
 
+SH_LAUNCH_COUNTERS = 1
+
+
 class ShLaunch(ctypes.Structure):
-    _fields_ = [("waves_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+    _fields_ = [("waves_per_cu", ctypes.c_uint32), ("ops_per_wave", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ShStats(ctypes.Structure):
@@ -46,7 +50,9 @@ class ShStats(ctypes.Structure):
                 ("pool_capacity", ctypes.c_uint64), ("error_word", ctypes.c_uint32),
                 ("violations", ctypes.c_uint32), ("num_buckets", ctypes.c_uint32),
                 ("hash_a", ctypes.c_uint32), ("hash_b", ctypes.c_uint32),
-                ("hash_p", ctypes.c_uint32)]
+                ("hash_p", ctypes.c_uint32), ("rounds", ctypes.c_uint64),
+                ("cas_lost", ctypes.c_uint64), ("allocs", ctypes.c_uint64),
+                ("link_lost", ctypes.c_uint64), ("block_moves", ctypes.c_uint64)]
 
 
 class SlabHashError(RuntimeError):
@@ -157,8 +163,8 @@ def sh_destroy(t) -> None:
     _check("sh_destroy", lib().sh_destroy(t))
 
 
-def sh_set_launch(t, waves_per_cu: int = 0) -> None:
-    shape = ShLaunch(int(waves_per_cu))
+def sh_set_launch(t, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0) -> None:
+    shape = ShLaunch(int(waves_per_cu), int(ops_per_wave), int(flags))
     _check("sh_set_launch", lib().sh_set_launch(t, ctypes.byref(shape)))
 
 
@@ -267,8 +273,8 @@ class SlabHash:
     def reset(self, stream=None):
         sh_reset(self.handle, stream)
 
-    def set_launch(self, waves_per_cu: int):
-        sh_set_launch(self.handle, waves_per_cu)
+    def set_launch(self, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0):
+        sh_set_launch(self.handle, waves_per_cu, ops_per_wave, flags)
 
     def insert(self, keys, vals, stream=None, status=True):
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None

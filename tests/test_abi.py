@@ -27,12 +27,14 @@ def test_exports_every_declared_symbol(lib):
 
 def test_storage_bytes(lib):
     p = S.ShParams(4096, 4 * 2048, 12345, 678)
-    want = 256 + 4096 * 256 + 4 * 2048 * 256 + 4 * 256
+    hdr = 4096  # header + counter slots
+    want = hdr + 4096 * 256 + 4 * 2048 * 256 + 4 * 256
     assert S.sh_storage_bytes(p) == want
-    assert S.sh_storage_bytes(S.ShParams(1, 0, 1, 0)) == 256 + 256
-    # invalid: zero buckets, pool not a multiple of 2048, a = 0, a >= p, b >= p
+    assert S.sh_storage_bytes(S.ShParams(1, 0, 1, 0)) == hdr + 256
+    # invalid: zero buckets, pool not a multiple of 2048, a = 0, a >= p, b >= p, B + P too big
     for bad in [S.ShParams(0, 0, 1, 0), S.ShParams(8, 100, 1, 0), S.ShParams(8, 0, 0, 0),
-                S.ShParams(8, 0, S.SH_HASH_PRIME, 0), S.ShParams(8, 0, 1, S.SH_HASH_PRIME)]:
+                S.ShParams(8, 0, S.SH_HASH_PRIME, 0), S.ShParams(8, 0, 1, S.SH_HASH_PRIME),
+                S.ShParams(0xFFFFFFFF - 2048, 2048, 1, 0)]:
         assert S.sh_storage_bytes(bad) == 0
 
 
