@@ -38,6 +38,20 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
               0.8: 55174}
 
 
+# Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
+# a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
+# source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
+TRAFFIC_SRC_SHA = "abe8f75237fc802b"
+TRAFFIC_BYTES = {"build": 1463722613, "search_hit": 1038286130, "search_miss": 1038286130,
+                 "mixed": 19452702, "reset": 94478514}
+
+
+def source_sha() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_1710_11246_amd", "csrc", "slabhash.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -98,6 +112,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="also time build/search at every utilisation target")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed region, copy 1 GiB device-to-device once (a reference "
+                         "for scaling hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the slab hash here is built and timed on a "
@@ -199,6 +216,7 @@ def main():
             (n_ins + n_miss) * v_miss + (n_del + n_hit) * v_hit) + 8.0 * (n_ins + n_del),
         "reset": float(table.storage.numel()),
     }
+    traffic_ok = source_sha() == TRAFFIC_SRC_SHA
     kernels = {}
     for k in names:
         gbs = bytes_l[k] / (avg_ms[k] * 1e-3) / 1e9
@@ -209,11 +227,23 @@ def main():
                       "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
         if n_ops:
             kernels[k]["Mops"] = round(n_ops / (avg_ms[k] * 1e-3) / 1e6, 1)
+        kernels[k]["traffic_bytes"] = TRAFFIC_BYTES[k] if traffic_ok else None
     dom = max((k for k in names if k != "reset"), key=lambda k: per_step_ms[k])
     ach = bytes_l[dom] / (avg_ms[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": TRAFFIC_BYTES[dom] if traffic_ok else None, "kernel": dom,
             "bytes_per_launch": int(bytes_l[dom])}
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (src.numel() * 4,
+                                                                 src.numel() * 4))
+        del src, dst
 
     sweep = None
     if args.sweep:
