@@ -114,7 +114,8 @@ sh_status_t sh_create(const sh_params_t *p, void *d_storage, size_t bytes, void 
 /* Re-initialise the table in place (same as the initialisation done by sh_create). */
 sh_status_t sh_reset(sh_table_t *t, void *stream);
 
-/* Free the host handle only; the device storage stays the caller's. */
+/* Free the host handle only; the device storage stays the caller's. Handles that belong to a
+   multi-table object (sh_multi_table) give SH_EINVAL. */
 sh_status_t sh_destroy(sh_table_t *t);
 
 /* Set the launch shape used by later calls on this table (NULL restores the default).
@@ -165,6 +166,68 @@ sh_status_t sh_stats(sh_table_t *t, sh_stats_t *h_out, void *stream);
 sh_status_t sh_dump(sh_table_t *t, uint32_t *d_bucket, uint32_t *d_key, uint32_t *d_val,
                     uint64_t cap, uint32_t *d_bucket_counts, uint64_t *d_count,
                     uint32_t *d_violations, void *stream);
+
+/* ---- Batched form: many tables, one launch ------------------------------------------------
+   A multi-table object holds T independent slab hashes (each with its own buckets, pool and
+   hash) in one caller-owned device allocation, plus a device directory of them. One call runs
+   the ops of many per-table batches in a single persistent kernel launch; that launch can be
+   captured once into a HIP graph and replayed. */
+
+#define SH_MAX_BATCHES 4096u /* descriptors per batched launch */
+
+/* Ops [offset, offset + length) of the shared op arrays go to table `table`. */
+typedef struct {
+    uint64_t offset;
+    uint32_t length;
+    uint32_t table;
+} sh_batch_desc_t;
+
+typedef struct sh_multi sh_multi_t;
+typedef struct sh_graph sh_graph_t;
+
+/* Device bytes for T tables with these parameters (directory + each table's storage, each
+   256-byte aligned). Returns 0 if T == 0 or any parameter set is invalid. */
+size_t sh_multi_storage_bytes(uint32_t T, const sh_params_t *h_params);
+
+/* Bind T tables to caller-owned storage (256-byte aligned, at least sh_multi_storage_bytes) and
+   enqueue their initialisation and the directory upload on `stream`. */
+sh_status_t sh_multi_create(uint32_t T, const sh_params_t *h_params, void *d_storage,
+                            size_t bytes, void *stream, sh_multi_t **out);
+
+/* Handle of table t for the single-table calls (build, search, stats, dump, ...). It stays
+   owned by the multi-table object: sh_destroy rejects it with SH_EINVAL. */
+sh_status_t sh_multi_table(sh_multi_t *m, uint32_t t, sh_table_t **out);
+
+/* Launch shape for sh_multi_mixed (same fields as sh_set_launch). */
+sh_status_t sh_multi_set_launch(sh_multi_t *m, const sh_launch_t *shape);
+
+/* Run nb batches (d_desc, device memory, nb <= SH_MAX_BATCHES) in one launch. The op arrays
+   (d_ops, d_keys, d_vals_in, d_vals_out, d_status) hold n_ops entries. Each batch is a
+   concurrent mixed batch on its table with the semantics of sh_mixed; batches on different
+   tables are independent, and several batches on one table run concurrently with each other.
+   Descriptor contents are read on the device at run time, so a captured launch can be replayed
+   with new descriptors and ops written into the same buffers. On the device, a descriptor
+   naming a table >= T is skipped and ranges are clipped to [0, n_ops); overlapping ranges give
+   unspecified results for the overlapping ops. nb == 0 or n_ops == 0 is a no-op. */
+sh_status_t sh_multi_mixed(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_t nb,
+                           const uint8_t *d_ops, const uint32_t *d_keys,
+                           const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,
+                           uint64_t n_ops, void *stream);
+
+/* Capture one sh_multi_mixed launch with these arguments into an executable HIP graph. The
+   graph reads the same buffers on every replay. */
+sh_status_t sh_multi_graph(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_t nb,
+                           const uint8_t *d_ops, const uint32_t *d_keys,
+                           const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,
+                           uint64_t n_ops, sh_graph_t **out);
+
+/* Replay a captured graph on `stream`. */
+sh_status_t sh_graph_launch(sh_graph_t *g, void *stream);
+
+sh_status_t sh_graph_destroy(sh_graph_t *g);
+
+/* Free the host objects only; the device storage stays the caller's. */
+sh_status_t sh_multi_destroy(sh_multi_t *m);
 
 /* Short description of a status code. */
 const char *sh_strerror(sh_status_t s);

@@ -37,6 +37,7 @@ constexpr int kWavesPerBlock = kBlock / 64;
 constexpr size_t kHeaderBytes = 4096;   // Header, then the counter slots
 constexpr uint32_t kCounterSlots = 32;   // 64-byte slots of 8 counters, one per wavefront % 32
 constexpr uint32_t kFlagCounters = SH_LAUNCH_COUNTERS;
+constexpr uint32_t kMaxBatches = SH_MAX_BATCHES;
 constexpr uint32_t kDefaultWavesPerCU = 16;
 
 enum Kind { kSearch = 0, kInsert = 1, kDelete = 2, kMixed = 3 };
@@ -244,6 +245,231 @@ struct Counters {
 enum : uint32_t { kMsgFound = 1, kMsgEnd = 2, kMsgMove = 3, kMsgGrow = 4, kMsgSwapIns = 5,
                   kMsgSwapRep = 6, kMsgSwapDel = 7 };
 
+// Per-wavefront LDS: cursor slab index, key and op kind of each op, and each op's outcome cell.
+struct WaveLds {
+    uint32_t u[64];
+    uint32_t key[64];
+    uint32_t op[64];
+    uint64_t msg[64];
+};
+
+// One chunk of up to 64 ops (lane l < count holds op base + l) on table T, processed in rounds
+// until every op has finished (see the description above).
+template <int K>
+__device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
+                          const uint8_t *__restrict__ ops, const uint32_t *__restrict__ keys,
+                          const uint32_t *__restrict__ vals, uint32_t *__restrict__ vout,
+                          uint8_t *__restrict__ sout, uint64_t base, uint32_t count,
+                          uint32_t flags)
+{
+    constexpr bool kCoherent = (K != kSearch);
+    constexpr bool kHasIns = (K == kInsert || K == kMixed);
+    const uint32_t lane = lane_id();
+    const uint32_t half = lane >> 5, slot = lane & 31;
+    const bool is31 = slot == 31;
+    const uint32_t below = (1u << slot) - 1u; // slots of my half below mine
+    const uint32_t hshift = lane & 32;
+    const uint64_t *lane_base = T.base + slot; // this lane's slot of slab 0
+    const uint64_t i = base + lane;
+    const bool in = lane < count;
+    const uint32_t key = in ? keys[i] : kEmpty;
+    uint32_t val = 0;
+    if constexpr (kHasIns)
+        val = in ? vals[i] : 0;
+    uint32_t op = (uint32_t)K;
+    if constexpr (K == kMixed)
+        op = in ? (uint32_t)ops[i] : 0u;
+    const bool reserved = in && key == kEmpty;
+    const uint64_t res_m = ballot(reserved);
+    if (res_m)
+        raise_error(T, SH_ERR_RESERVED_KEY, lane, ffs0(res_m));
+    const bool act = in && !reserved && op <= 2;
+    const uint32_t bkt = act ? bucket_of(key, T.a, T.b, T.B) : 0u;
+    L.key[lane] = key;
+    if constexpr (K == kMixed)
+        L.op[lane] = op;
+
+    uint32_t rv = kEmpty, rs = 0; // this lane's results
+    uint32_t loc = kEmpty;        // this lane's cursor
+    uint64_t todo = ballot(act);
+    while (todo) {
+        ++cnt.rounds;
+        // ---- 1. load ----
+        L.u[lane] = ((todo >> lane) & 1) ? ((loc == kEmpty) ? bkt : T.B + loc) : 0u;
+        __builtin_amdgcn_wave_barrier();
+        uint64_t pre[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const uint32_t u = L.u[2 * q + half];
+            pre[q] = load_slot<kCoherent>(lane_base + (size_t)u * 32);
+        }
+        // ---- 2. decide: the target lane of each op writes the op's outcome ----
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            if (!((todo >> (2 * q)) & 3ull))
+                continue;
+            const uint64_t w = pre[q];
+            const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+            const uint32_t kq = L.key[2 * q + half];
+            const bool is_key = !is31 && lo == kq;
+            const uint32_t kh = (uint32_t)(ballot(is_key) >> hshift); // my half's key votes
+            bool ins = (K == kInsert);
+            uint32_t code_key = (K == kSearch) ? kMsgFound
+                                               : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
+            if constexpr (K == kMixed) {
+                const uint32_t oq = L.op[2 * q + half];
+                ins = oq == kInsert;
+                code_key = (oq == kSearch) ? kMsgFound
+                                           : ((oq == kDelete) ? kMsgSwapDel : kMsgSwapRep);
+            }
+            bool target;
+            uint32_t code;
+            if constexpr (kHasIns) {
+                const bool is_empty = !is31 && w == kEmptyPair;
+                const uint32_t eh = (uint32_t)(ballot(is_empty) >> hshift);
+                const bool first_empty = ins && is_empty && (eh & below) == 0u;
+                const bool tail = is31 && (!ins || eh == 0u);
+                target = is_key || (kh == 0u && (first_empty || tail));
+                code = is_key ? code_key
+                              : (first_empty ? kMsgSwapIns
+                                             : (hi != kEmpty ? kMsgMove
+                                                             : (ins ? kMsgGrow : kMsgEnd)));
+            } else {
+                target = is_key || (kh == 0u && is31);
+                code = is_key ? code_key : (hi != kEmpty ? kMsgMove : kMsgEnd);
+            }
+            if (target)
+                L.msg[2 * q + half] = ((uint64_t)((code << 8) | slot) << 32) | hi;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // ---- 3. act on the outcome ----
+        const bool mine = (todo >> lane) & 1;
+        const uint64_t msg = mine ? L.msg[lane] : 0ull;
+        const uint32_t payload = (uint32_t)msg;
+        const uint32_t code = mine ? (uint32_t)(msg >> 40) : 0u;
+        const uint32_t tslot = (uint32_t)(msg >> 32) & 255u;
+        if (code == kMsgFound) {
+            rv = payload;
+            rs = 1;
+        }
+        if (code == kMsgMove)
+            loc = payload;
+        bool done = code == kMsgFound || code == kMsgEnd;
+        uint64_t alloc_m = 0;
+        if constexpr (K != kSearch) {
+            bool won = false, lost = false;
+            if (code >= kMsgSwapIns) {
+                uint32_t cslot = tslot;
+                uint64_t *slab = T.base + (size_t)((loc == kEmpty) ? bkt : T.B + loc) * 32;
+                const uint64_t desired =
+                    (code == kMsgSwapDel) ? kTombPair : (((uint64_t)val << 32) | key);
+                uint64_t expect = (code == kMsgSwapIns) ? kEmptyPair
+                                                        : (((uint64_t)payload << 32) | key);
+                uint64_t old = cas64(slab + cslot, expect, desired);
+                if (old == expect) {
+                    rs = (code == kMsgSwapRep) ? 2u : 1u;
+                    won = true;
+                } else if (code == kMsgSwapIns) {
+                    // Walk forward from the lost empty slot using the occupants the swaps
+                    // return; at most the 31 slots of this slab.
+                    for (;;) {
+                        if ((uint32_t)old == key) { // the same key was inserted: replace it
+                            expect = old;
+                            old = cas64(slab + cslot, expect, desired);
+                            if (old == expect) {
+                                rs = 2u;
+                                won = true;
+                            } else {
+                                lost = true;
+                            }
+                            break;
+                        }
+                        if (++cslot >= 31) {
+                            lost = true; // slab filled up: the next round follows `next`
+                            break;
+                        }
+                        old = cas64(slab + cslot, kEmptyPair, desired);
+                        if (old == kEmptyPair) {
+                            rs = 1u;
+                            won = true;
+                            break;
+                        }
+                    }
+                } else {
+                    lost = true;
+                }
+            }
+            done = done || won;
+            if (flags & kFlagCounters)
+                cnt.cas_lost += (uint32_t)__popcll(ballot(lost));
+            alloc_m = ballot(code == kMsgGrow);
+        }
+        todo &= ~ballot(done);
+        if constexpr (K != kSearch) {
+            // ---- 4. allocate and link new tail slabs, one op at a time ----
+            while (alloc_m) {
+                const uint32_t j = ffs0(alloc_m);
+                alloc_m &= alloc_m - 1;
+                const uint32_t lj = rl(loc, j), bj = rl(bkt, j);
+                uint64_t *tail = T.base + (size_t)((lj == kEmpty) ? bj : T.B + lj) * 32;
+                const uint32_t idx = wave_alloc(T, al, lane);
+                if (idx == kEmpty) {
+                    raise_error(T, SH_ERR_POOL_EXHAUSTED, lane, 0);
+                    todo &= ~(1ull << j); // status stays 0
+                    continue;
+                }
+                ++cnt.allocs;
+                uint32_t *link = reinterpret_cast<uint32_t *>(tail + 31) + 1;
+                uint32_t old = 0;
+                if (lane == 0)
+                    old = cas32(link, kEmpty, idx);
+                old = rl(old, 0);
+                if (old == kEmpty) {
+                    loc = wl(loc, j, idx);
+                } else {
+                    ++cnt.link_lost;
+                    if (lane == 0)
+                        slab_free(T, idx); // another wavefront linked first
+                    loc = wl(loc, j, old);
+                }
+            }
+        }
+        // Every load of this round has been consumed; saying so lets the compiler issue the
+        // next round's loads back to back instead of waiting before each one.
+        wait_vm_all();
+    }
+
+    if (in) {
+        if (vout)
+            vout[i] = rv;
+        if (sout)
+            sout[i] = (uint8_t)rs;
+    }
+}
+
+__device__ __forceinline__ void flush_counters(const View &T, const Counters &cnt,
+                                               const Alloc &al, uint32_t wave)
+{
+    if (lane_id() == 0) {
+        unsigned long long *cs = T.counters + (size_t)(wave % kCounterSlots) * 8;
+        atomicAdd(cs + 0, (unsigned long long)cnt.rounds);
+        atomicAdd(cs + 1, (unsigned long long)cnt.cas_lost);
+        atomicAdd(cs + 2, (unsigned long long)cnt.allocs);
+        atomicAdd(cs + 3, (unsigned long long)cnt.link_lost);
+        atomicAdd(cs + 4, (unsigned long long)al.total_moves);
+    }
+}
+
+__device__ __forceinline__ void alloc_init(Alloc &al, uint32_t wave, uint32_t seq)
+{
+    al.blk = kEmpty;
+    al.word = 0;
+    al.moves = 0;
+    al.total_moves = 0;
+    al.full = false;
+    al.start = mix32(wave * 0x9E3779B9u + seq);
+}
+
 template <int K>
 __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__restrict__ ops,
                                                      const uint32_t *__restrict__ keys,
@@ -252,217 +478,110 @@ __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__re
                                                      uint8_t *__restrict__ sout, uint32_t seq,
                                                      uint32_t C, uint32_t flags)
 {
-    constexpr bool kCoherent = (K != kSearch);
-    constexpr bool kHasIns = (K == kInsert || K == kMixed);
-    // Per wavefront: cursor slab index, key and op kind of each op, and each op's outcome cell.
-    __shared__ uint32_t s_u[kWavesPerBlock][64];
-    __shared__ uint32_t s_key[kWavesPerBlock][64];
-    __shared__ uint32_t s_op[kWavesPerBlock][64];
-    __shared__ uint64_t s_msg[kWavesPerBlock][64];
+    __shared__ WaveLds lds[kWavesPerBlock];
     const uint32_t wl_ = threadIdx.x >> 6;
-    const uint32_t lane = lane_id();
-    const uint32_t half = lane >> 5, slot = lane & 31;
-    const bool is31 = slot == 31;
-    const uint32_t below = (1u << slot) - 1u; // slots of my half below mine
-    const uint32_t hshift = lane & 32;
     const uint32_t wave = blockIdx.x * kWavesPerBlock + wl_;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    const uint64_t *lane_base = T.base + slot; // this lane's slot of slab 0
     Alloc al;
-    al.blk = kEmpty;
-    al.word = 0;
-    al.moves = 0;
-    al.total_moves = 0;
-    al.full = false;
-    al.start = mix32(wave * 0x9E3779B9u + seq);
+    alloc_init(al, wave, seq);
     Counters cnt = {0, 0, 0, 0};
-
     const uint64_t nchunks = (n + C - 1) / C;
     for (uint64_t c = wave; c < nchunks; c += nwaves) {
-        const uint64_t i = c * C + lane;
-        const bool in = lane < C && i < n;
-        const uint32_t key = in ? keys[i] : kEmpty;
-        uint32_t val = 0;
-        if constexpr (kHasIns)
-            val = in ? vals[i] : 0;
-        uint32_t op = (uint32_t)K;
-        if constexpr (K == kMixed)
-            op = in ? (uint32_t)ops[i] : 0u;
-        const bool reserved = in && key == kEmpty;
-        const uint64_t res_m = ballot(reserved);
-        if (res_m)
-            raise_error(T, SH_ERR_RESERVED_KEY, lane, ffs0(res_m));
-        const bool act = in && !reserved && op <= 2;
-        const uint32_t bkt = act ? bucket_of(key, T.a, T.b, T.B) : 0u;
-        s_key[wl_][lane] = key;
-        if constexpr (K == kMixed)
-            s_op[wl_][lane] = op;
-
-        uint32_t rv = kEmpty, rs = 0; // this lane's results
-        uint32_t loc = kEmpty;        // this lane's cursor
-        uint64_t todo = ballot(act);
-        while (todo) {
-            ++cnt.rounds;
-            // ---- 1. load ----
-            s_u[wl_][lane] = ((todo >> lane) & 1) ? ((loc == kEmpty) ? bkt : T.B + loc) : 0u;
-            __builtin_amdgcn_wave_barrier();
-            uint64_t pre[32];
-#pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                const uint32_t u = s_u[wl_][2 * q + half];
-                pre[q] = load_slot<kCoherent>(lane_base + (size_t)u * 32);
-            }
-            // ---- 2. decide: the target lane of each op writes the op's outcome ----
-#pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                if (!((todo >> (2 * q)) & 3ull))
-                    continue;
-                const uint64_t w = pre[q];
-                const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-                const uint32_t kq = s_key[wl_][2 * q + half];
-                const bool is_key = !is31 && lo == kq;
-                const uint32_t kh = (uint32_t)(ballot(is_key) >> hshift); // my half's key votes
-                bool ins = (K == kInsert);
-                uint32_t code_key = (K == kSearch) ? kMsgFound
-                                                   : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
-                if constexpr (K == kMixed) {
-                    const uint32_t oq = s_op[wl_][2 * q + half];
-                    ins = oq == kInsert;
-                    code_key = (oq == kSearch) ? kMsgFound
-                                               : ((oq == kDelete) ? kMsgSwapDel : kMsgSwapRep);
-                }
-                bool target;
-                uint32_t code;
-                if constexpr (kHasIns) {
-                    const bool is_empty = !is31 && w == kEmptyPair;
-                    const uint32_t eh = (uint32_t)(ballot(is_empty) >> hshift);
-                    const bool first_empty = ins && is_empty && (eh & below) == 0u;
-                    const bool tail = is31 && (!ins || eh == 0u);
-                    target = is_key || (kh == 0u && (first_empty || tail));
-                    code = is_key ? code_key
-                                  : (first_empty ? kMsgSwapIns
-                                                 : (hi != kEmpty ? kMsgMove
-                                                                 : (ins ? kMsgGrow : kMsgEnd)));
-                } else {
-                    target = is_key || (kh == 0u && is31);
-                    code = is_key ? code_key : (hi != kEmpty ? kMsgMove : kMsgEnd);
-                }
-                if (target)
-                    s_msg[wl_][2 * q + half] = ((uint64_t)((code << 8) | slot) << 32) | hi;
-            }
-            __builtin_amdgcn_wave_barrier();
-            // ---- 3. act on the outcome ----
-            const bool mine = (todo >> lane) & 1;
-            const uint64_t msg = mine ? s_msg[wl_][lane] : 0ull;
-            const uint32_t payload = (uint32_t)msg;
-            const uint32_t code = mine ? (uint32_t)(msg >> 40) : 0u;
-            const uint32_t tslot = (uint32_t)(msg >> 32) & 255u;
-            if (code == kMsgFound) {
-                rv = payload;
-                rs = 1;
-            }
-            if (code == kMsgMove)
-                loc = payload;
-            bool done = code == kMsgFound || code == kMsgEnd;
-            uint64_t alloc_m = 0;
-            if constexpr (K != kSearch) {
-                bool won = false, lost = false;
-                if (code >= kMsgSwapIns) {
-                    uint32_t cslot = tslot;
-                    uint64_t *slab = T.base + (size_t)((loc == kEmpty) ? bkt : T.B + loc) * 32;
-                    const uint64_t desired =
-                        (code == kMsgSwapDel) ? kTombPair : (((uint64_t)val << 32) | key);
-                    uint64_t expect = (code == kMsgSwapIns) ? kEmptyPair
-                                                            : (((uint64_t)payload << 32) | key);
-                    uint64_t old = cas64(slab + cslot, expect, desired);
-                    if (old == expect) {
-                        rs = (code == kMsgSwapRep) ? 2u : 1u;
-                        won = true;
-                    } else if (code == kMsgSwapIns) {
-                        // Walk forward from the lost empty slot using the occupants the swaps
-                        // return; at most the 31 slots of this slab.
-                        for (;;) {
-                            if ((uint32_t)old == key) { // the same key was inserted: replace it
-                                expect = old;
-                                old = cas64(slab + cslot, expect, desired);
-                                if (old == expect) {
-                                    rs = 2u;
-                                    won = true;
-                                } else {
-                                    lost = true;
-                                }
-                                break;
-                            }
-                            if (++cslot >= 31) {
-                                lost = true; // slab filled up: the next round follows `next`
-                                break;
-                            }
-                            old = cas64(slab + cslot, kEmptyPair, desired);
-                            if (old == kEmptyPair) {
-                                rs = 1u;
-                                won = true;
-                                break;
-                            }
-                        }
-                    } else {
-                        lost = true;
-                    }
-                }
-                done = done || won;
-                if (flags & kFlagCounters)
-                    cnt.cas_lost += (uint32_t)__popcll(ballot(lost));
-                alloc_m = ballot(code == kMsgGrow);
-            }
-            todo &= ~ballot(done);
-            if constexpr (K != kSearch) {
-                // ---- 4. allocate and link new tail slabs, one op at a time ----
-                while (alloc_m) {
-                    const uint32_t j = ffs0(alloc_m);
-                    alloc_m &= alloc_m - 1;
-                    const uint32_t lj = rl(loc, j), bj = rl(bkt, j);
-                    uint64_t *tail = T.base + (size_t)((lj == kEmpty) ? bj : T.B + lj) * 32;
-                    const uint32_t idx = wave_alloc(T, al, lane);
-                    if (idx == kEmpty) {
-                        raise_error(T, SH_ERR_POOL_EXHAUSTED, lane, 0);
-                        todo &= ~(1ull << j); // status stays 0
-                        continue;
-                    }
-                    ++cnt.allocs;
-                    uint32_t *link = reinterpret_cast<uint32_t *>(tail + 31) + 1;
-                    uint32_t old = 0;
-                    if (lane == 0)
-                        old = cas32(link, kEmpty, idx);
-                    old = rl(old, 0);
-                    if (old == kEmpty) {
-                        loc = wl(loc, j, idx);
-                    } else {
-                        ++cnt.link_lost;
-                        if (lane == 0)
-                            slab_free(T, idx); // another wavefront linked first
-                        loc = wl(loc, j, old);
-                    }
-                }
-            }
-            // Every load of this round has been consumed; saying so lets the compiler issue the
-            // next round's loads back to back instead of waiting before each one.
-            wait_vm_all();
-        }
-
-        if (in) {
-            if (vout)
-                vout[i] = rv;
-            if (sout)
-                sout[i] = (uint8_t)rs;
-        }
+        const uint64_t base = c * C;
+        const uint32_t count = (uint32_t)((n - base < C) ? n - base : C);
+        run_chunk<K>(T, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base, count, flags);
     }
-    if ((flags & kFlagCounters) && lane == 0) {
-        unsigned long long *cs = T.counters + (size_t)(wave % kCounterSlots) * 8;
-        atomicAdd(cs + 0, (unsigned long long)cnt.rounds);
-        atomicAdd(cs + 1, (unsigned long long)cnt.cas_lost);
-        atomicAdd(cs + 2, (unsigned long long)cnt.allocs);
-        atomicAdd(cs + 3, (unsigned long long)cnt.link_lost);
-        atomicAdd(cs + 4, (unsigned long long)al.total_moves);
+    if (flags & kFlagCounters)
+        flush_counters(T, cnt, al, wave);
+}
+
+// Batched form: many tables, one launch. d_desc[d] hands ops [offset, offset + length) of the
+// shared op arrays (n_ops long) to table `table` (< T); descriptors naming another table are
+// skipped and ranges are clipped to the arrays, so no descriptor makes the kernel read or write
+// outside them. Each block turns the descriptors' chunk counts into an
+// exclusive prefix sum in LDS; wavefront w then takes global chunks w, w + W, ... of the
+// concatenated chunk space and finds each chunk's descriptor by binary search. Nothing is
+// counted with atomics, so the launch can be captured in a graph and replayed as is.
+__global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ dir, uint32_t T,
+                                                       const sh_batch_desc_t *__restrict__ desc,
+                                                       uint32_t nb, uint64_t n_ops,
+                                                       const uint8_t *__restrict__ ops,
+                                                       const uint32_t *__restrict__ keys,
+                                                       const uint32_t *__restrict__ vals,
+                                                       uint32_t *__restrict__ vout,
+                                                       uint8_t *__restrict__ sout, uint32_t seq,
+                                                       uint32_t C, uint32_t flags)
+{
+    __shared__ WaveLds lds[kWavesPerBlock];
+    __shared__ uint32_t pre[kMaxBatches + 1];
+    __shared__ uint32_t part[kBlock];
+    const uint32_t tid = threadIdx.x;
+    // exclusive prefix of chunk counts: each thread sums a contiguous segment, then the
+    // segment sums are scanned across the block
+    const uint32_t seg = (nb + kBlock - 1) / kBlock;
+    const uint32_t s0 = tid * seg, s1 = (s0 + seg < nb) ? s0 + seg : nb;
+    uint32_t local = 0;
+    for (uint32_t d = s0; d < s1; ++d)
+        local += (desc[d].length + C - 1) / C;
+    part[tid] = local;
+    __syncthreads();
+    for (uint32_t off = 1; off < kBlock; off <<= 1) {
+        const uint32_t v = (tid >= off) ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
     }
+    uint32_t run = part[tid] - local; // exclusive start of this thread's segment
+    for (uint32_t d = s0; d < s1; ++d) {
+        pre[d] = run;
+        run += (desc[d].length + C - 1) / C;
+    }
+    if (tid == kBlock - 1)
+        pre[nb] = part[kBlock - 1];
+    __syncthreads();
+
+    const uint32_t wl_ = tid >> 6;
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + wl_;
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const uint32_t total = pre[nb];
+    Alloc al;
+    alloc_init(al, wave, seq);
+    Counters cnt = {0, 0, 0, 0};
+    uint32_t cur_t = kEmpty;
+    for (uint32_t c = wave; c < total; c += nwaves) {
+        // largest d with pre[d] <= c (descriptors with no ops have pre[d] == pre[d + 1])
+        uint32_t lo = 0, hi = nb;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pre[mid] <= c)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const sh_batch_desc_t dd = desc[lo];
+        if (dd.table >= T)
+            continue; // no such table: the batch is skipped
+        if (dd.table != cur_t) {
+            if ((flags & kFlagCounters) && cur_t != kEmpty) {
+                flush_counters(dir[cur_t], cnt, al, wave);
+                cnt = Counters{0, 0, 0, 0};
+            }
+            alloc_init(al, wave, seq); // another table: another pool
+            cur_t = dd.table;
+        }
+        const View Tv = dir[cur_t];
+        const uint64_t first = (uint64_t)(c - pre[lo]) * C;
+        const uint64_t base = dd.offset + first;
+        uint64_t count = (dd.length - first < C) ? dd.length - first : C;
+        if (base >= n_ops)
+            count = 0; // range outside the op arrays: nothing is read or written
+        else if (count > n_ops - base)
+            count = n_ops - base;
+        run_chunk<kMixed>(Tv, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base,
+                          (uint32_t)count, flags);
+    }
+    if ((flags & kFlagCounters) && cur_t != kEmpty)
+        flush_counters(dir[cur_t], cnt, al, wave);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -611,6 +730,23 @@ struct sh_table {
     uint32_t ops_per_wave; // 0 = chosen per call
     uint32_t flags;        // SH_LAUNCH_* bits
     int num_cu;
+    int embedded; // owned by a multi-table object
+};
+
+struct sh_multi {
+    uint32_t T;
+    sh_table *tables; // T embedded table handles
+    View *h_dir;      // host copy of the device directory
+    View *d_dir;
+    char *storage;
+    size_t bytes;
+    uint32_t seq, waves_per_cu, ops_per_wave, flags;
+    int num_cu;
+};
+
+struct sh_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
 };
 
 namespace {
@@ -729,6 +865,85 @@ sh_status_t walk(sh_table *t, uint32_t *dbkt, uint32_t *dkey, uint32_t *dval, ui
     return SH_OK;
 }
 
+sh_status_t device_cus(int *ncu)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return SH_EHIP;
+    if (*ncu <= 0)
+        *ncu = 1;
+    return SH_OK;
+}
+
+// Fill a host handle for a table whose storage (already validated) starts at `storage`.
+void bind_table(sh_table *t, const sh_params_t *p, char *storage, size_t bytes, int ncu)
+{
+    Layout L;
+    layout_of(p, &L);
+    t->p = *p;
+    t->storage = storage;
+    t->bytes = bytes;
+    t->num_cu = ncu;
+    t->waves_per_cu = kDefaultWavesPerCU;
+    t->ops_per_wave = 0;
+    t->flags = 0;
+    t->seq = 0;
+    t->v.hdr = reinterpret_cast<Header *>(storage);
+    t->v.counters = reinterpret_cast<unsigned long long *>(storage + 256);
+    t->v.base = reinterpret_cast<uint64_t *>(storage + L.base);
+    t->v.pool = reinterpret_cast<uint64_t *>(storage + L.pool);
+    t->v.bitmap = reinterpret_cast<uint32_t *>(storage + L.bitmap);
+    t->v.B = p->num_buckets;
+    t->v.a = p->hash_a;
+    t->v.b = p->hash_b;
+    t->v.pool_slabs = p->pool_slabs;
+    t->v.nblk = p->pool_slabs / SH_BLOCK_SLABS;
+}
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Directory first, then each table's storage, all 256-byte aligned. offs[t] (if given) gets the
+// byte offset of table t. Returns 0 for invalid input.
+size_t multi_layout(uint32_t T, const sh_params_t *p, size_t *offs)
+{
+    if (T == 0 || !p)
+        return 0;
+    size_t off = round256((size_t)T * sizeof(View));
+    for (uint32_t t = 0; t < T; ++t) {
+        Layout L;
+        if (!layout_of(&p[t], &L))
+            return 0;
+        if (offs)
+            offs[t] = off;
+        off += round256(L.total);
+    }
+    return off;
+}
+
+sh_status_t launch_multi(sh_multi *m, const sh_batch_desc_t *d_desc, uint32_t nb,
+                         const uint8_t *d_ops, const uint32_t *d_keys, const uint32_t *d_vals_in,
+                         uint32_t *d_vals_out, uint8_t *d_status, uint64_t n_ops,
+                         hipStream_t stream)
+{
+    uint32_t C = m->ops_per_wave;
+    const uint64_t waves = (uint64_t)m->num_cu * m->waves_per_cu;
+    if (!C) {
+        C = 64;
+        while (C > 8 && 2 * ((n_ops + C - 1) / C) < waves)
+            C >>= 1;
+    }
+    uint64_t w = waves;
+    const uint64_t chunks = (n_ops + C - 1) / C + nb; // at most one partial chunk each
+    if (w > chunks)
+        w = chunks;
+    const uint32_t blocks = (uint32_t)((w + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(multi_kernel, dim3(blocks ? blocks : 1), dim3(kBlock), 0, stream,
+                       m->d_dir, m->T, d_desc, nb, n_ops, d_ops, d_keys, d_vals_in, d_vals_out,
+                       d_status, m->seq++, C, m->flags);
+    return check_launch();
+}
+
 } // namespace
 
 extern "C" {
@@ -746,29 +961,13 @@ sh_status_t sh_create(const sh_params_t *p, void *d_storage, size_t bytes, void 
     if (!out || !d_storage || !layout_of(p, &L) || bytes < L.total ||
         (reinterpret_cast<uintptr_t>(d_storage) & 255u))
         return SH_EINVAL;
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    int ncu = 0;
+    if (device_cus(&ncu) != SH_OK)
         return SH_EHIP;
     sh_table *t = static_cast<sh_table *>(calloc(1, sizeof(sh_table)));
     if (!t)
         return SH_ENOMEM;
-    t->p = *p;
-    t->storage = static_cast<char *>(d_storage);
-    t->bytes = bytes;
-    t->num_cu = ncu > 0 ? ncu : 1;
-    t->waves_per_cu = kDefaultWavesPerCU;
-    t->seq = 0;
-    t->v.hdr = reinterpret_cast<Header *>(t->storage);
-    t->v.counters = reinterpret_cast<unsigned long long *>(t->storage + 256);
-    t->v.base = reinterpret_cast<uint64_t *>(t->storage + L.base);
-    t->v.pool = reinterpret_cast<uint64_t *>(t->storage + L.pool);
-    t->v.bitmap = reinterpret_cast<uint32_t *>(t->storage + L.bitmap);
-    t->v.B = p->num_buckets;
-    t->v.a = p->hash_a;
-    t->v.b = p->hash_b;
-    t->v.pool_slabs = p->pool_slabs;
-    t->v.nblk = p->pool_slabs / SH_BLOCK_SLABS;
+    bind_table(t, p, static_cast<char *>(d_storage), bytes, ncu);
     sh_status_t s = launch_init(t, stream);
     if (s != SH_OK) {
         free(t);
@@ -787,7 +986,7 @@ sh_status_t sh_reset(sh_table_t *t, void *stream)
 
 sh_status_t sh_destroy(sh_table_t *t)
 {
-    if (!t)
+    if (!t || t->embedded)
         return SH_EINVAL;
     free(t);
     return SH_OK;
@@ -897,6 +1096,184 @@ sh_status_t sh_dump(sh_table_t *t, uint32_t *d_bucket, uint32_t *d_key, uint32_t
         return SH_EINVAL;
     return walk(t, d_bucket, d_key, d_val, cap, d_bucket_counts, 1, d_count, d_violations,
                 stream);
+}
+
+size_t sh_multi_storage_bytes(uint32_t T, const sh_params_t *h_params)
+{
+    return multi_layout(T, h_params, nullptr);
+}
+
+sh_status_t sh_multi_create(uint32_t T, const sh_params_t *h_params, void *d_storage,
+                            size_t bytes, void *stream, sh_multi_t **out)
+{
+    if (!out || !d_storage || (reinterpret_cast<uintptr_t>(d_storage) & 255u))
+        return SH_EINVAL;
+    const size_t need = multi_layout(T, h_params, nullptr);
+    if (need == 0 || bytes < need)
+        return SH_EINVAL;
+    int ncu = 0;
+    if (device_cus(&ncu) != SH_OK)
+        return SH_EHIP;
+    sh_multi *m = static_cast<sh_multi *>(calloc(1, sizeof(sh_multi)));
+    size_t *offs = static_cast<size_t *>(calloc(T, sizeof(size_t)));
+    if (m) {
+        m->tables = static_cast<sh_table *>(calloc(T, sizeof(sh_table)));
+        m->h_dir = static_cast<View *>(calloc(T, sizeof(View)));
+    }
+    if (!m || !offs || !m->tables || !m->h_dir) {
+        if (m) {
+            free(m->tables);
+            free(m->h_dir);
+        }
+        free(m);
+        free(offs);
+        return SH_ENOMEM;
+    }
+    multi_layout(T, h_params, offs);
+    m->T = T;
+    m->storage = static_cast<char *>(d_storage);
+    m->bytes = bytes;
+    m->d_dir = reinterpret_cast<View *>(d_storage);
+    m->num_cu = ncu;
+    m->waves_per_cu = kDefaultWavesPerCU;
+    sh_status_t s = SH_OK;
+    for (uint32_t t = 0; t < T && s == SH_OK; ++t) {
+        Layout L;
+        layout_of(&h_params[t], &L);
+        bind_table(&m->tables[t], &h_params[t], m->storage + offs[t], L.total, ncu);
+        m->tables[t].embedded = 1;
+        m->h_dir[t] = m->tables[t].v;
+        s = launch_init(&m->tables[t], stream);
+    }
+    free(offs);
+    if (s == SH_OK &&
+        (hipMemcpyAsync(m->d_dir, m->h_dir, (size_t)T * sizeof(View), hipMemcpyHostToDevice,
+                        S(stream)) != hipSuccess ||
+         hipStreamSynchronize(S(stream)) != hipSuccess))
+        s = SH_EHIP;
+    if (s != SH_OK) {
+        free(m->tables);
+        free(m->h_dir);
+        free(m);
+        return s;
+    }
+    *out = m;
+    return SH_OK;
+}
+
+sh_status_t sh_multi_table(sh_multi_t *m, uint32_t t, sh_table_t **out)
+{
+    if (!m || !out || t >= m->T)
+        return SH_EINVAL;
+    *out = &m->tables[t];
+    return SH_OK;
+}
+
+sh_status_t sh_multi_set_launch(sh_multi_t *m, const sh_launch_t *shape)
+{
+    if (!m)
+        return SH_EINVAL;
+    if (!shape) {
+        m->waves_per_cu = kDefaultWavesPerCU;
+        m->ops_per_wave = 0;
+        m->flags = 0;
+        return SH_OK;
+    }
+    const uint32_t c = shape->ops_per_wave;
+    if (shape->waves_per_cu > 64 || (c != 0 && c != 8 && c != 16 && c != 32 && c != 64) ||
+        (shape->flags & ~(uint32_t)SH_LAUNCH_COUNTERS))
+        return SH_EINVAL;
+    m->waves_per_cu = shape->waves_per_cu ? shape->waves_per_cu : kDefaultWavesPerCU;
+    m->ops_per_wave = c;
+    m->flags = shape->flags;
+    return SH_OK;
+}
+
+sh_status_t sh_multi_mixed(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_t nb,
+                           const uint8_t *d_ops, const uint32_t *d_keys,
+                           const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,
+                           uint64_t n_ops, void *stream)
+{
+    if (!m || nb > kMaxBatches || n_ops >= (1ull << 40))
+        return SH_EINVAL;
+    if (nb == 0 || n_ops == 0)
+        return SH_OK;
+    if (!d_desc || !d_ops || !d_keys || !d_vals_in || !d_vals_out || !d_status)
+        return SH_EINVAL;
+    return launch_multi(m, d_desc, nb, d_ops, d_keys, d_vals_in, d_vals_out, d_status, n_ops,
+                        S(stream));
+}
+
+sh_status_t sh_multi_graph(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_t nb,
+                           const uint8_t *d_ops, const uint32_t *d_keys,
+                           const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,
+                           uint64_t n_ops, sh_graph_t **out)
+{
+    if (!m || !out || nb == 0 || nb > kMaxBatches || n_ops == 0 || n_ops >= (1ull << 40) ||
+        !d_desc || !d_ops || !d_keys || !d_vals_in || !d_vals_out || !d_status)
+        return SH_EINVAL;
+    sh_graph *g = static_cast<sh_graph *>(calloc(1, sizeof(sh_graph)));
+    if (!g)
+        return SH_ENOMEM;
+    hipStream_t cs = nullptr;
+    sh_status_t s = SH_OK;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        free(g);
+        return SH_EHIP;
+    }
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        s = SH_EHIP;
+    } else {
+        s = launch_multi(m, d_desc, nb, d_ops, d_keys, d_vals_in, d_vals_out, d_status, n_ops,
+                         cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (s == SH_OK && e != hipSuccess)
+            s = SH_EHIP;
+        if (s == SH_OK) {
+            g->graph = graph;
+            if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                s = SH_EHIP;
+        } else if (graph) {
+            hipGraphDestroy(graph);
+        }
+    }
+    hipStreamDestroy(cs);
+    if (s != SH_OK) {
+        if (g->graph)
+            hipGraphDestroy(g->graph);
+        free(g);
+        return s;
+    }
+    *out = g;
+    return SH_OK;
+}
+
+sh_status_t sh_graph_launch(sh_graph_t *g, void *stream)
+{
+    if (!g)
+        return SH_EINVAL;
+    return hipGraphLaunch(g->exec, S(stream)) == hipSuccess ? SH_OK : SH_EHIP;
+}
+
+sh_status_t sh_graph_destroy(sh_graph_t *g)
+{
+    if (!g)
+        return SH_EINVAL;
+    hipGraphExecDestroy(g->exec);
+    hipGraphDestroy(g->graph);
+    free(g);
+    return SH_OK;
+}
+
+sh_status_t sh_multi_destroy(sh_multi_t *m)
+{
+    if (!m)
+        return SH_EINVAL;
+    free(m->tables);
+    free(m->h_dir);
+    free(m);
+    return SH_OK;
 }
 
 const char *sh_strerror(sh_status_t s)

@@ -29,6 +29,7 @@ SH_HASH_PRIME = 4294967291
 SH_SLAB_BYTES = 256
 SH_SLAB_PAIRS = 31
 SH_BLOCK_SLABS = 2048
+SH_MAX_BATCHES = 4096
 
 
 class ShParams(ctypes.Structure):
@@ -76,6 +77,15 @@ _SIGS = {
     "sh_stats": ([_P, _P, _P], ctypes.c_int),
     "sh_dump": ([_P, _P, _P, _P, _U64, _P, _P, _P, _P], ctypes.c_int),
     "sh_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "sh_multi_storage_bytes": ([_U32, _P], _SZ),
+    "sh_multi_create": ([_U32, _P, _P, _SZ, _P, _P], ctypes.c_int),
+    "sh_multi_table": ([_P, _U32, _P], ctypes.c_int),
+    "sh_multi_set_launch": ([_P, _P], ctypes.c_int),
+    "sh_multi_mixed": ([_P, _P, _U32, _P, _P, _P, _P, _P, _U64, _P], ctypes.c_int),
+    "sh_multi_graph": ([_P, _P, _U32, _P, _P, _P, _P, _P, _U64, _P], ctypes.c_int),
+    "sh_graph_launch": ([_P, _P], ctypes.c_int),
+    "sh_graph_destroy": ([_P], ctypes.c_int),
+    "sh_multi_destroy": ([_P], ctypes.c_int),
 }
 
 _lib = None
@@ -221,6 +231,91 @@ def sh_dump(t, bucket, key, val, bucket_counts, count, violations, stream=None) 
 
 
 # ---------------------------------------------------------------------------------------------
+# Batched form
+
+def _params_array(params):
+    arr = (ShParams * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p
+    return arr
+
+
+def sh_multi_storage_bytes(params) -> int:
+    return int(lib().sh_multi_storage_bytes(len(params), _params_array(params)))
+
+
+def sh_multi_create(params, storage: torch.Tensor, stream=None) -> ctypes.c_void_p:
+    if not isinstance(storage, torch.Tensor) or not storage.is_cuda or \
+            not storage.is_contiguous():
+        raise ValueError("storage must be a contiguous CUDA tensor")
+    out = ctypes.c_void_p()
+    nbytes = storage.numel() * storage.element_size()
+    _check("sh_multi_create", lib().sh_multi_create(len(params), _params_array(params),
+                                                    storage.data_ptr(), nbytes, _stream(stream),
+                                                    ctypes.byref(out)))
+    return out
+
+
+def sh_multi_table(m, t: int) -> ctypes.c_void_p:
+    out = ctypes.c_void_p()
+    _check("sh_multi_table", lib().sh_multi_table(m, int(t), ctypes.byref(out)))
+    return out
+
+
+def sh_multi_set_launch(m, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0):
+    shape = ShLaunch(int(waves_per_cu), int(ops_per_wave), int(flags))
+    _check("sh_multi_set_launch", lib().sh_multi_set_launch(m, ctypes.byref(shape)))
+
+
+def _multi_args(desc, nb, ops, keys, vals_in, vals_out, status):
+    n = keys.numel()
+    if nb > SH_MAX_BATCHES:
+        raise ValueError("at most %d batches per launch" % SH_MAX_BATCHES)
+    return (_dev(desc, "desc", (torch.int64,), 2 * nb), nb, _dev(ops, "ops", (torch.uint8,), n),
+            _dev(keys, "keys", _U32_TYPES), _dev(vals_in, "vals_in", _U32_TYPES, n),
+            _dev(vals_out, "vals_out", _U32_TYPES, n), _dev(status, "status", (torch.uint8,), n))
+
+
+def sh_multi_mixed(m, desc, nb, ops, keys, vals_in, vals_out, status, stream=None) -> None:
+    """desc: int64 device tensor of 2*nb words (see pack_batch_descs); the op arrays' length
+    is keys.numel()."""
+    _check("sh_multi_mixed", lib().sh_multi_mixed(
+        m, *_multi_args(desc, nb, ops, keys, vals_in, vals_out, status), keys.numel(),
+        _stream(stream)))
+
+
+def sh_multi_graph(m, desc, nb, ops, keys, vals_in, vals_out, status) -> ctypes.c_void_p:
+    out = ctypes.c_void_p()
+    _check("sh_multi_graph", lib().sh_multi_graph(
+        m, *_multi_args(desc, nb, ops, keys, vals_in, vals_out, status), keys.numel(),
+        ctypes.byref(out)))
+    return out
+
+
+def sh_graph_launch(g, stream=None) -> None:
+    _check("sh_graph_launch", lib().sh_graph_launch(g, _stream(stream)))
+
+
+def sh_graph_destroy(g) -> None:
+    _check("sh_graph_destroy", lib().sh_graph_destroy(g))
+
+
+def sh_multi_destroy(m) -> None:
+    _check("sh_multi_destroy", lib().sh_multi_destroy(m))
+
+
+def pack_batch_descs(offsets, lengths, tables) -> np.ndarray:
+    """sh_batch_desc_t records {uint64 offset; uint32 length; uint32 table} as int64 pairs."""
+    off = np.asarray(offsets, dtype=np.uint64)
+    ln = np.asarray(lengths, dtype=np.uint64)
+    tb = np.asarray(tables, dtype=np.uint64)
+    out = np.empty((off.size, 2), dtype=np.uint64)
+    out[:, 0] = off
+    out[:, 1] = ln | (tb << np.uint64(32))
+    return out.reshape(-1).view(np.int64)
+
+
+# ---------------------------------------------------------------------------------------------
 # Conveniences for tests and the benchmark (still only marshalling).
 
 def to_dev(a: np.ndarray, device="cuda") -> torch.Tensor:
@@ -245,21 +340,27 @@ def pool_slabs_bound(n_inserts: int, concurrency_slack_blocks: int = 4) -> int:
 
 
 class SlabHash:
-    """A table plus the torch tensor that holds its device storage."""
+    """A table plus the torch tensor that holds its device storage (or, with `handle`, a view of
+    a table owned by a MultiSlabHash)."""
 
     def __init__(self, num_buckets: int, pool_slabs: int, hash_a: int, hash_b: int,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, handle=None, owner=None):
         self.params = ShParams(int(num_buckets), int(pool_slabs), int(hash_a), int(hash_b))
+        self.device = device
+        self.owner = owner
+        if handle is not None:
+            self.storage = None
+            self.handle = handle
+            return
         nbytes = sh_storage_bytes(self.params)
         if nbytes == 0:
             raise ValueError("invalid table parameters")
         self.storage = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.handle = sh_create(self.params, self.storage, stream)
-        self.device = device
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and getattr(self, "owner", None) is None:
             try:
                 sh_destroy(h)
             except Exception:
@@ -324,3 +425,37 @@ class SlabHash:
         order = np.lexsort((k, b))
         return (b[order], k[order], v[order], to_host_u32(counts).reshape(-1, 3),
                 int(viol.item()))
+
+
+class MultiSlabHash:
+    """T tables in one device allocation, driven by one launch per round of batches."""
+
+    def __init__(self, params, device="cuda", stream=None):
+        self.params = list(params)
+        nbytes = sh_multi_storage_bytes(self.params)
+        if nbytes == 0:
+            raise ValueError("invalid multi-table parameters")
+        self.storage = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.handle = sh_multi_create(self.params, self.storage, stream)
+        self.device = device
+        self.tables = [SlabHash(p.num_buckets, p.pool_slabs, p.hash_a, p.hash_b, device,
+                                handle=sh_multi_table(self.handle, t), owner=self)
+                       for t, p in enumerate(self.params)]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                sh_multi_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def set_launch(self, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0):
+        sh_multi_set_launch(self.handle, waves_per_cu, ops_per_wave, flags)
+
+    def mixed(self, desc, nb, ops, keys, vals, stream=None):
+        vo = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+        st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        sh_multi_mixed(self.handle, desc, nb, ops, keys, vals, vo, st, stream)
+        return vo, st

@@ -220,3 +220,120 @@ def gamma_counts(length: int, fractions) -> tuple[int, int, int, int]:
     else:
         n_hit = 0
     return n_ins, n_del, n_hit, rest - n_hit
+
+
+def sample_distinct(rng: SplitMix64, k: int, n: int, ok: np.ndarray | None = None) -> np.ndarray:
+    """k distinct indices in [0, n) (optionally only where ok[idx]), in draw order."""
+    avail = n if ok is None else int(np.count_nonzero(ok[:n]))
+    if k > avail:
+        raise ValueError("cannot draw %d distinct indices from %d" % (k, avail))
+    out = np.empty(0, dtype=np.int64)
+    while out.size < k:
+        need = k - out.size
+        cand = rng.below(need + need // 4 + 16, n)
+        if ok is not None:
+            cand = cand[ok[cand]]
+        allc = np.concatenate([out, cand])
+        _, first = np.unique(allc, return_index=True)
+        first.sort()
+        out = allc[first]
+    return out[:k]
+
+
+@dataclass
+class MultiRounds:
+    """Batched workload: T tables, each bulk-built with n[t] keys, then `rounds` rounds in which
+    every table receives one mixed batch. Round r's ops are concatenated table by table; batch
+    (r, t) is ops [offsets[r][t], offsets[r][t] + lengths[r][t]) of the round's arrays."""
+    seed: int
+    hash_a: np.ndarray
+    hash_b: np.ndarray
+    init_keys: list
+    init_vals: list
+    ops: list
+    keys: list
+    vals: list
+    offsets: list
+    lengths: list
+    final_occupancy: np.ndarray
+
+
+def multi_rounds(seed: int, T: int, n_lo: int, n_hi: int, len_lo: int, len_hi: int,
+                 rounds: int, fractions, prime: int) -> MultiRounds:
+    """Tables with log-uniform sizes in [n_lo, n_hi] and per-round batch lengths log-uniform in
+    [len_lo, len_hi]. fractions = (insert new, delete existing, search existing, search absent)
+    of each batch (the paper's operation distribution). Keys are unique within a table; at
+    most one mutation per key per batch; searches of existing keys and deletes draw from the
+    keys live at the start of the round. A batch never deletes more keys than are live: the
+    shortfall (and all existing-key searches of a table with no live key) become searches of
+    absent keys, so every batch keeps its length."""
+    rng = SplitMix64(seed)
+    n = log_uniform_ints(rng, T, n_lo, n_hi)
+    lens = log_uniform_ints(rng, rounds * T, len_lo, len_hi).reshape(rounds, T)
+    counts = [[list(gamma_counts(int(lens[r, t]), fractions)) for t in range(T)]
+              for r in range(rounds)]
+    ha = np.empty(T, np.int64)
+    hb = np.empty(T, np.int64)
+    universe, alive, nxt, absent = [], [], [], []
+    init_keys, init_vals = [], []
+    for t in range(T):
+        ha[t], hb[t] = hash_params(rng, prime)
+        n_ins = sum(counts[r][t][0] for r in range(rounds))
+        n_abs = max(counts[r][t][3] + counts[r][t][1] + counts[r][t][2]
+                    for r in range(rounds)) + 1
+        u = unique_keys(rng, int(n[t]) + n_ins + n_abs)
+        universe.append(u[: int(n[t]) + n_ins])
+        absent.append(u[int(n[t]) + n_ins:])
+        a = np.zeros(int(n[t]) + n_ins, dtype=bool)
+        a[: int(n[t])] = True
+        alive.append(a)
+        nxt.append(int(n[t]))
+        init_keys.append(u[: int(n[t])])
+        init_vals.append(value_of(u[: int(n[t])]))
+    occ = n.astype(np.int64).copy()
+    R_ops, R_keys, R_vals, R_off, R_len = [], [], [], [], []
+    for r in range(rounds):
+        parts_o, parts_k, offs, lns = [], [], [], []
+        off = 0
+        for t in range(T):
+            n_ins, n_del, n_hit, n_miss = counts[r][t]
+            live_idx_ok = alive[t].copy()
+            n_live = int(np.count_nonzero(live_idx_ok[: nxt[t]]))
+            if n_del > n_live:
+                n_miss += n_del - n_live
+                n_del = n_live
+            if n_live == 0:
+                n_miss += n_hit
+                n_hit = 0
+            dels = sample_distinct(rng, n_del, nxt[t], live_idx_ok[: nxt[t]]) if n_del else \
+                np.empty(0, np.int64)
+            hits = np.empty(0, np.int64)
+            if n_hit:
+                hits = rng.below(n_hit * 2 + 16, nxt[t])
+                hits = hits[live_idx_ok[hits]][:n_hit]
+                while hits.size < n_hit:
+                    h2 = rng.below(n_hit, nxt[t])
+                    hits = np.concatenate([hits, h2[live_idx_ok[h2]]])[:n_hit]
+            ins = universe[t][nxt[t]: nxt[t] + n_ins]
+            miss = absent[t][rng.below(n_miss, absent[t].size)] if n_miss else \
+                np.empty(0, np.uint32)
+            k = np.concatenate([ins, universe[t][dels], universe[t][hits], miss]).astype(np.uint32)
+            o = np.concatenate([np.full(n_ins, OP_INSERT), np.full(n_del, OP_DELETE),
+                                np.full(n_hit + n_miss, OP_SEARCH)]).astype(np.uint8)
+            perm = rng.permutation(k.size)
+            parts_k.append(k[perm])
+            parts_o.append(o[perm])
+            offs.append(off)
+            lns.append(k.size)
+            off += k.size
+            alive[t][dels] = False
+            alive[t][nxt[t]: nxt[t] + n_ins] = True
+            nxt[t] += n_ins
+            occ[t] += n_ins
+        keys = np.concatenate(parts_k)
+        R_keys.append(keys)
+        R_ops.append(np.concatenate(parts_o))
+        R_vals.append(value_of(keys) ^ np.uint32(r + 1))
+        R_off.append(np.asarray(offs, dtype=np.int64))
+        R_len.append(np.asarray(lns, dtype=np.int64))
+    return MultiRounds(seed, ha, hb, init_keys, init_vals, R_ops, R_keys, R_vals, R_off, R_len, occ)

@@ -4,6 +4,7 @@ device."""
 import ctypes
 import os
 
+import numpy as np
 import pytest
 
 from paper_1710_11246_amd import slabhash as S
@@ -71,3 +72,29 @@ def test_pool_bound_holds_worst_case():
     for n in [1, 31, 32, 1000, 2048 * 31 + 5]:
         assert S.pool_slabs_bound(n, 0) >= -(-n // 31) - 1
         assert S.pool_slabs_bound(n) % 2048 == 0
+
+
+def test_multi_argument_errors(lib):
+    p = (S.ShParams * 2)(S.ShParams(16, 0, 3, 5), S.ShParams(100, 2048, 7, 9))
+    one = S.sh_storage_bytes(S.ShParams(16, 0, 3, 5))
+    two = S.sh_storage_bytes(S.ShParams(100, 2048, 7, 9))
+    rnd = lambda x: (x + 255) // 256 * 256
+    assert lib.sh_multi_storage_bytes(2, p) == rnd(2 * 64) + rnd(one) + rnd(two)
+    assert lib.sh_multi_storage_bytes(0, p) == 0
+    bad = (S.ShParams * 2)(S.ShParams(16, 0, 3, 5), S.ShParams(0, 0, 1, 0))
+    assert lib.sh_multi_storage_bytes(2, bad) == 0
+    out = ctypes.c_void_p()
+    assert lib.sh_multi_create(2, p, 257, 1 << 30, None, ctypes.byref(out)) == S.SH_EINVAL
+    assert lib.sh_multi_create(2, p, 256, 16, None, ctypes.byref(out)) == S.SH_EINVAL
+    assert lib.sh_multi_create(0, p, 256, 1 << 30, None, ctypes.byref(out)) == S.SH_EINVAL
+    assert lib.sh_multi_mixed(None, 256, 1, 256, 256, 256, 256, 256, 10, None) == S.SH_EINVAL
+    assert lib.sh_multi_graph(None, 256, 1, 256, 256, 256, 256, 256, 10, None) == S.SH_EINVAL
+    assert lib.sh_multi_table(None, 0, ctypes.byref(out)) == S.SH_EINVAL
+    assert lib.sh_multi_set_launch(None, None) == S.SH_EINVAL
+    assert lib.sh_graph_launch(None, None) == S.SH_EINVAL
+    assert lib.sh_graph_destroy(None) == S.SH_EINVAL
+    assert lib.sh_multi_destroy(None) == S.SH_EINVAL
+    d = S.pack_batch_descs([0, 7], [7, 3], [1, 2]).view(np.uint8).reshape(2, 16)
+    assert int.from_bytes(bytes(d[1, :8]), "little") == 7
+    assert int.from_bytes(bytes(d[1, 8:12]), "little") == 3
+    assert int.from_bytes(bytes(d[1, 12:16]), "little") == 2

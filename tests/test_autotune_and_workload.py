@@ -1,0 +1,86 @@
+"""CPU checks of the table-sizing model, the launch tuner's bookkeeping and the batched-workload
+generator."""
+import numpy as np
+import pytest
+
+from paper_1710_11246_amd import autotune as A
+from paper_1710_11246_amd import workload as W
+
+
+@pytest.mark.parametrize("target", [0.2, 0.4, 0.6, 0.7, 0.8])
+def test_buckets_for_utilisation_is_largest(target):
+    n = 1 << 20
+    B = A.buckets_for_utilisation(n, target)
+    assert A.utilisation(n, B) >= target
+    assert A.utilisation(n, B + 1) < target or B + 1 > n
+
+
+def test_pool_size_covers_oracle_use(oracle_mod):
+    rng = W.SplitMix64(8)
+    for n, target in [(1 << 14, 0.6), (1 << 17, 0.7), (1 << 16, 0.8), (3000, 0.9)]:
+        keys = W.unique_keys(rng, n)
+        B = A.buckets_for_utilisation(n, target)
+        a, b = W.hash_params(rng, oracle_mod.PRIME)
+        o = oracle_mod.Oracle(B, 31, a, b)
+        o.replace(keys, keys)
+        pool = A.pool_slabs_for(n, B)
+        assert pool % 2048 == 0 and pool >= o.pool_used
+        # the model's expected utilisation is close to the realised one
+        assert abs(o.utilisation(8, 8) - A.utilisation(n, B)) < 0.02
+
+
+def test_tune_launch_picks_fastest_and_caches(tmp_path, monkeypatch):
+    monkeypatch.setenv("SLABHASH_TUNE_CACHE", str(tmp_path / "c.json"))
+    cost = {(8, 16): 3.0, (16, 64): 1.0, (32, 32): 2.0}
+    calls = []
+
+    def run(w, c):
+        calls.append((w, c))
+        return cost[(w, c)]
+    shape, t = A.tune_launch("mixed", 1 << 16, run, "dev", candidates=list(cost))
+    assert shape == (16, 64) and len(calls) == 9
+    shape2, _ = A.tune_launch("mixed", 1 << 16, run, "dev", candidates=list(cost))
+    assert shape2 == (16, 64) and len(calls) == 9  # served from the cache
+
+
+def test_sample_distinct_refuses_impossible_draws():
+    with pytest.raises(ValueError):
+        W.sample_distinct(W.SplitMix64(1), 5, 4)
+    ok = np.array([True, False, True, False])
+    assert sorted(W.sample_distinct(W.SplitMix64(1), 2, 4, ok).tolist()) == [0, 2]
+    with pytest.raises(ValueError):
+        W.sample_distinct(W.SplitMix64(1), 3, 4, ok)
+
+
+@pytest.mark.parametrize("n_lo,len_hi", [(64, 2048), (4, 4096)])
+def test_multi_rounds_generator_properties(n_lo, len_hi):
+    mr = W.multi_rounds(seed=4, T=12, n_lo=n_lo, n_hi=4096, len_lo=1, len_hi=len_hi, rounds=4,
+                        fractions=(0.3, 0.1, 0.3, 0.3), prime=4294967291)
+    live = [dict(zip(k.tolist(), v.tolist())) for k, v in zip(mr.init_keys, mr.init_vals)]
+    for t in range(12):
+        assert np.unique(mr.init_keys[t]).size == mr.init_keys[t].size
+    for r in range(4):
+        ops, keys = mr.ops[r], mr.keys[r]
+        assert mr.lengths[r].sum() == keys.size and mr.offsets[r][0] == 0
+        for t in range(12):
+            o = ops[mr.offsets[r][t]: mr.offsets[r][t] + mr.lengths[r][t]]
+            k = keys[mr.offsets[r][t]: mr.offsets[r][t] + mr.lengths[r][t]]
+            v = mr.vals[r][mr.offsets[r][t]: mr.offsets[r][t] + mr.lengths[r][t]]
+            mut = k[o != 0]
+            assert np.unique(mut).size == mut.size          # one mutation per key per batch
+            n_live = len(live[t])
+            assert int((o == W.OP_DELETE).sum()) <= n_live   # never more deletes than live keys
+            for op, key, val in zip(o.tolist(), k.tolist(), v.tolist()):
+                if op == W.OP_INSERT:
+                    assert key not in live[t]               # inserts are fresh keys
+                if op == W.OP_DELETE:
+                    assert key in live[t]                   # deletes hit live keys
+            for op, key, val in zip(o.tolist(), k.tolist(), v.tolist()):
+                if op == W.OP_INSERT:
+                    live[t][key] = val
+                elif op == W.OP_DELETE:
+                    del live[t][key]
+    occ = [mr.init_keys[t].size + sum(int((mr.ops[r][mr.offsets[r][t]: mr.offsets[r][t] +
+                                                      mr.lengths[r][t]] == 1).sum())
+                                          for r in range(4)) for t in range(12)]
+    assert list(mr.final_occupancy) == occ
