@@ -102,6 +102,118 @@ def cpu_baseline(wl, batches, B):
                       "searches, 16 mixed batches of 2^16 (%.1f s)" % dt}
 
 
+def run_batched(seed: int = 31, T: int = 256, rounds: int = 20, wpc_override: int = 0):
+    """Batched workload: T tables with log-uniform sizes in [2^10, 2^20] (bulk-built), then
+    `rounds` rounds in each of which every table gets one mixed batch of log-uniform length in
+    [2^6, 2^16] (30% insert new / 10% delete existing / 60% search, half existing, half absent).
+    Buckets and pools come from the autotuner's Binomial model for utilisation 0.6 at each
+    table's final occupancy; the batched launch shape is picked by timing candidates on round 0.
+    Three forms run the same rounds on identically built tables: one sh_mixed launch per table,
+    one batched launch per round, and one graph replay per round (after copying the round's
+    descriptors into the graph's buffer). Returns a dict of results."""
+    import torch
+    from paper_1710_11246_amd import autotune as A
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    t0 = time.perf_counter()
+    mr = W.multi_rounds(seed=seed, T=T, n_lo=1 << 10, n_hi=1 << 20, len_lo=1 << 6,
+                        len_hi=1 << 16, rounds=rounds, fractions=(0.3, 0.1, 0.3, 0.3),
+                        prime=S.SH_HASH_PRIME)
+    params = []
+    for t in range(T):
+        occ = int(mr.final_occupancy[t])
+        B = A.buckets_for_utilisation(occ, 0.6)
+        params.append(S.ShParams(B, A.pool_slabs_for(occ, B), int(mr.hash_a[t]),
+                                 int(mr.hash_b[t])))
+    log("batched inputs: %d tables, %d rounds, %d ops/round avg (%.1f s)" % (
+        T, rounds, sum(k.size for k in mr.keys) // rounds, time.perf_counter() - t0))
+    m = S.MultiSlabHash(params)
+    init_k = [S.to_dev(k) for k in mr.init_keys]
+    init_v = [S.to_dev(v) for v in mr.init_vals]
+    sizes = [k.size for k in mr.keys]
+    offs = np.cumsum([0] + sizes)
+    all_ops = S.to_dev(np.concatenate(mr.ops))
+    all_keys = S.to_dev(np.concatenate(mr.keys))
+    all_vals = S.to_dev(np.concatenate(mr.vals))
+    n_all = int(offs[-1])
+    vout = torch.empty(n_all, dtype=torch.int32, device="cuda")
+    sout = torch.empty(n_all, dtype=torch.uint8, device="cuda")
+    h_descs = [S.pack_batch_descs(mr.offsets[r] + offs[r], mr.lengths[r], range(T))
+               for r in range(rounds)]
+    descs = [S.to_dev(d) for d in h_descs]
+
+    def rebuild():
+        for t, tb in enumerate(m.tables):
+            tb.reset()
+        for t, tb in enumerate(m.tables):
+            S.sh_build(tb.handle, init_k[t], init_v[t], None)
+        torch.cuda.synchronize()
+
+    def timed(fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    # launch shape for the batched form, tuned on round 0
+    def run_shape(wpc, c):
+        rebuild()
+        S.sh_multi_set_launch(m.handle, wpc, c)
+        return timed(lambda: S.sh_multi_mixed(m.handle, descs[0], T, all_ops, all_keys,
+                                              all_vals, vout, sout))
+    shape, timings = A.tune_launch("multi_mixed", sizes[0], run_shape,
+                                   torch.cuda.get_device_name(), use_cache=False)
+    if wpc_override:
+        shape = (wpc_override, shape[1])
+    S.sh_multi_set_launch(m.handle, *shape)
+
+    # (i) one sh_mixed launch per table, issued from C
+    rebuild()
+    t_plain = timed(lambda: [S.sh_multi_mixed_each(m.handle, h_descs[r], all_ops, all_keys,
+                                                   all_vals, vout, sout) for r in range(rounds)])
+    st_plain = sout.clone()
+    # (ii) one batched launch per round
+    rebuild()
+    t_batched = timed(lambda: [S.sh_multi_mixed(m.handle, descs[r], T, all_ops, all_keys,
+                                                all_vals, vout, sout) for r in range(rounds)])
+    mut = torch.from_numpy(np.concatenate(mr.ops) != 0).to("cuda")
+    same_plain = bool(((sout == st_plain) | ~mut).all())
+    # (iii) graph replay per round
+    rebuild()
+    desc_buf = torch.empty_like(descs[0])
+    g = S.sh_multi_graph(m.handle, desc_buf, T, all_ops, all_keys, all_vals, vout, sout)
+    try:
+        def graphed():
+            for r in range(rounds):
+                desc_buf.copy_(descs[r])
+                S.sh_graph_launch(g)
+        t_graph = timed(graphed)
+    finally:
+        S.sh_graph_destroy(g)
+    same_graph = bool(((sout == st_plain) | ~mut).all())
+    stats = [tb.stats() for tb in m.tables[:4]]
+    res = {
+        "workload": "256 tables, n log-uniform [2^10, 2^20], 20 rounds of one batch per table, "
+                    "length log-uniform [2^6, 2^16], 30/10/60 insert/delete/search",
+        "tables": T, "rounds": rounds, "total_keys_built": int(sum(k.size for k in mr.init_keys)),
+        "ops": n_all, "launch_shape": list(shape),
+        "plain_ms_per_round": round(t_plain * 1e3 / rounds, 3),
+        "batched_ms_per_round": round(t_batched * 1e3 / rounds, 3),
+        "graph_ms_per_round": round(t_graph * 1e3 / rounds, 3),
+        "plain_Mops": round(n_all / t_plain / 1e6, 1),
+        "batched_Mops": round(n_all / t_batched / 1e6, 1),
+        "graph_Mops": round(n_all / t_graph / 1e6, 1),
+        "speedup_graph_vs_plain": round(t_plain / t_graph, 2),
+        "mutation_status_equal_to_plain": same_plain and same_graph,
+        "utilisation_first_tables": [round(8.0 * s["live"] / (256.0 * s["slabs_total"]), 3)
+                                     for s in stats],
+    }
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +224,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="also time build/search at every utilisation target")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device once (a reference "
                          "for scaling hardware traffic counters)")
@@ -272,6 +385,13 @@ def main():
                                 for nm, v in res.items()}}
             del tu
 
+    batched = None
+    if not args.no_batched:
+        del table
+        torch.cuda.empty_cache()
+        log("batched form")
+        batched = run_batched()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -306,6 +426,8 @@ def main():
     }
     if sweep is not None:
         out["sweep"] = sweep
+    if batched is not None:
+        out["batched"] = batched
     print(json.dumps(out), flush=True)
 
 

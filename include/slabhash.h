@@ -214,6 +214,15 @@ sh_status_t sh_multi_mixed(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_
                            const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,
                            uint64_t n_ops, void *stream);
 
+/* The same batches as sh_multi_mixed, but the plain way: one sh_mixed launch per descriptor,
+   issued in order on `stream` from host-side descriptors h_desc (nb of them, any number).
+   Descriptors naming a table >= T or a range outside [0, n_ops) give SH_EINVAL before anything
+   is enqueued. */
+sh_status_t sh_multi_mixed_each(sh_multi_t *m, const sh_batch_desc_t *h_desc, uint32_t nb,
+                                const uint8_t *d_ops, const uint32_t *d_keys,
+                                const uint32_t *d_vals_in, uint32_t *d_vals_out,
+                                uint8_t *d_status, uint64_t n_ops, void *stream);
+
 /* Capture one sh_multi_mixed launch with these arguments into an executable HIP graph. The
    graph reads the same buffers on every replay. */
 sh_status_t sh_multi_graph(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_t nb,

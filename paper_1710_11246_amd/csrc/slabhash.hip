@@ -1204,6 +1204,29 @@ sh_status_t sh_multi_mixed(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_
                         S(stream));
 }
 
+sh_status_t sh_multi_mixed_each(sh_multi_t *m, const sh_batch_desc_t *h_desc, uint32_t nb,
+                                const uint8_t *d_ops, const uint32_t *d_keys,
+                                const uint32_t *d_vals_in, uint32_t *d_vals_out,
+                                uint8_t *d_status, uint64_t n_ops, void *stream)
+{
+    if (!m || (nb && (!h_desc || !d_ops || !d_keys || !d_vals_in || !d_vals_out || !d_status)))
+        return SH_EINVAL;
+    for (uint32_t d = 0; d < nb; ++d)
+        if (h_desc[d].table >= m->T || h_desc[d].offset > n_ops ||
+            h_desc[d].length > n_ops - h_desc[d].offset)
+            return SH_EINVAL;
+    for (uint32_t d = 0; d < nb; ++d) {
+        const sh_batch_desc_t &b = h_desc[d];
+        const uint64_t o = b.offset;
+        const sh_status_t s =
+            launch_ops<kMixed>(&m->tables[b.table], d_ops + o, d_keys + o, d_vals_in + o, b.length,
+                               d_vals_out + o, d_status + o, stream);
+        if (s != SH_OK)
+            return s;
+    }
+    return SH_OK;
+}
+
 sh_status_t sh_multi_graph(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_t nb,
                            const uint8_t *d_ops, const uint32_t *d_keys,
                            const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,

@@ -83,6 +83,7 @@ _SIGS = {
     "sh_multi_set_launch": ([_P, _P], ctypes.c_int),
     "sh_multi_mixed": ([_P, _P, _U32, _P, _P, _P, _P, _P, _U64, _P], ctypes.c_int),
     "sh_multi_graph": ([_P, _P, _U32, _P, _P, _P, _P, _P, _U64, _P], ctypes.c_int),
+    "sh_multi_mixed_each": ([_P, _P, _U32, _P, _P, _P, _P, _P, _U64, _P], ctypes.c_int),
     "sh_graph_launch": ([_P, _P], ctypes.c_int),
     "sh_graph_destroy": ([_P], ctypes.c_int),
     "sh_multi_destroy": ([_P], ctypes.c_int),
@@ -282,6 +283,19 @@ def sh_multi_mixed(m, desc, nb, ops, keys, vals_in, vals_out, status, stream=Non
     _check("sh_multi_mixed", lib().sh_multi_mixed(
         m, *_multi_args(desc, nb, ops, keys, vals_in, vals_out, status), keys.numel(),
         _stream(stream)))
+
+
+def sh_multi_mixed_each(m, h_desc: np.ndarray, ops, keys, vals_in, vals_out, status,
+                        stream=None) -> None:
+    """The plain form: one sh_mixed launch per descriptor, issued from C. h_desc is the host
+    int64 array from pack_batch_descs."""
+    h = np.ascontiguousarray(h_desc, dtype=np.int64)
+    nb = h.size // 2
+    n = keys.numel()
+    _check("sh_multi_mixed_each", lib().sh_multi_mixed_each(
+        m, h.ctypes.data, nb, _dev(ops, "ops", (torch.uint8,), n), _dev(keys, "keys", _U32_TYPES),
+        _dev(vals_in, "vals_in", _U32_TYPES, n), _dev(vals_out, "vals_out", _U32_TYPES, n),
+        _dev(status, "status", (torch.uint8,), n), n, _stream(stream)))
 
 
 def sh_multi_graph(m, desc, nb, ops, keys, vals_in, vals_out, status) -> ctypes.c_void_p:

@@ -89,6 +89,7 @@ def test_multi_argument_errors(lib):
     assert lib.sh_multi_create(0, p, 256, 1 << 30, None, ctypes.byref(out)) == S.SH_EINVAL
     assert lib.sh_multi_mixed(None, 256, 1, 256, 256, 256, 256, 256, 10, None) == S.SH_EINVAL
     assert lib.sh_multi_graph(None, 256, 1, 256, 256, 256, 256, 256, 10, None) == S.SH_EINVAL
+    assert lib.sh_multi_mixed_each(None, 256, 1, 256, 256, 256, 256, 256, 10, None) == S.SH_EINVAL
     assert lib.sh_multi_table(None, 0, ctypes.byref(out)) == S.SH_EINVAL
     assert lib.sh_multi_set_launch(None, None) == S.SH_EINVAL
     assert lib.sh_graph_launch(None, None) == S.SH_EINVAL

@@ -93,11 +93,9 @@ def test_batched_equals_launch_per_table(oracle_mod):
         gv1, gs1 = m1.mixed(desc, 16, ops, keys, vals)
         gv2 = torch.empty_like(gv1)
         gs2 = torch.empty_like(gs1)
-        for t, tb in enumerate(m2.tables):
-            a, n = int(mr.offsets[r][t]), int(mr.lengths[r][t])
-            if n:
-                S.sh_mixed(tb.handle, ops[a:a + n], keys[a:a + n], vals[a:a + n],
-                           gv2[a:a + n], gs2[a:a + n])
+        S.sh_multi_mixed_each(m2.handle, S.pack_batch_descs(mr.offsets[r], mr.lengths[r],
+                                                            range(16)),
+                              ops, keys, vals, gv2, gs2)
         g1v, g1s = S.to_host_u32(gv1), gs1.cpu().numpy()
         g2v, g2s = S.to_host_u32(gv2), gs2.cpu().numpy()
         check_round(mr, r, oracles, g1v, g1s)
