@@ -238,6 +238,69 @@ sh_status_t sh_graph_destroy(sh_graph_t *g);
 /* Free the host objects only; the device storage stays the caller's. */
 sh_status_t sh_multi_destroy(sh_multi_t *m);
 
+/* ---- Served form: continuous batching -----------------------------------------------------
+   A server owns one table and a native request loop. Requests are ranges of ops already in the
+   server's device op arrays (n_ops entries; results go to the same positions of d_vals_out and
+   d_status). A request is admitted when fewer than max_requests are unfinished and the pool's
+   free slabs, minus those promised to unfinished requests and reserve_slabs, cover its worst
+   case (one new slab per insert). The loop gathers every admitted request not yet on the
+   device, up to max_batch_ops ops (and SH_MAX_BATCHES requests), into one launch of the
+   batched kernel, one descriptor per request; up to max_launches launches run at once on their
+   own streams, so work admitted while others run overlaps with them on the device. Requests
+   of one launch, and of launches in flight together, run concurrently: results are
+   linearizable, with requests that finished before another was admitted ordered before it. */
+
+typedef struct {
+    uint32_t max_launches;  /* launches in flight at once, 1..8 (0 = 4) */
+    uint32_t max_batch_ops; /* ops one launch takes at most (0 = 2^20); a larger request runs alone */
+    uint32_t max_requests;  /* admitted, unfinished requests at most (0 = 4096) */
+    uint32_t reserved0;
+    uint64_t reserve_slabs; /* pool slabs never promised to requests */
+} sh_server_cfg_t;
+
+typedef struct {
+    uint64_t offset;  /* ops [offset, offset + length) of the server's op arrays */
+    uint32_t length;
+    uint32_t inserts; /* insert ops among them: bounds the new slabs the request can need */
+} sh_request_t;
+
+typedef struct sh_server sh_server_t;
+
+/* Device scratch the server needs (directory + one descriptor buffer per launch slot). */
+size_t sh_server_scratch_bytes(const sh_server_cfg_t *cfg);
+
+/* Start serving table t. d_scratch: caller-owned device memory (256-byte aligned, at least
+   sh_server_scratch_bytes). Synchronises `stream` once to read the pool occupancy. No other call
+   may use the table while the server runs. */
+sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uint8_t *d_ops,
+                            const uint32_t *d_keys, const uint32_t *d_vals_in,
+                            uint32_t *d_vals_out, uint8_t *d_status, uint64_t n_ops,
+                            void *d_scratch, size_t scratch_bytes, void *stream,
+                            sh_server_t **out);
+
+/* Admit a request. SH_OK gives a ticket; SH_EBUSY means not admissible now (retry later);
+   SH_ENOMEM means it can never be admitted (its worst case exceeds the pool); SH_EINVAL for a
+   range outside the op arrays or an empty request. */
+sh_status_t sh_server_submit(sh_server_t *s, const sh_request_t *req, uint64_t *ticket);
+
+/* *done = 1 once the request's results are in device memory; times on sh_clock_ns's clock. */
+sh_status_t sh_server_poll(sh_server_t *s, uint64_t ticket, int *done, uint64_t *t_admit_ns,
+                           uint64_t *t_done_ns);
+
+/* Load driver: submit request i at time t0 + arrival_ns[i] (t0 = the call's start; arrival_ns
+   non-decreasing), keeping requests that are not yet admissible in arrival order, until all
+   have finished. admit_ns[i] and done_ns[i] (relative to t0) receive the admission and
+   completion times; a request that can never be admitted gets UINT64_MAX in both. */
+sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
+                             const uint64_t *h_arrival_ns, uint64_t n, uint64_t *h_admit_ns,
+                             uint64_t *h_done_ns);
+
+/* Finish all admitted work, stop the loop and free the server's host resources. */
+sh_status_t sh_server_stop(sh_server_t *s);
+
+/* The server's monotonic clock, in nanoseconds. */
+uint64_t sh_clock_ns(void);
+
 /* Short description of a status code. */
 const char *sh_strerror(sh_status_t s);
 

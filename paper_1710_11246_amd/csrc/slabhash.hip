@@ -23,6 +23,14 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
 #include "slabhash.h"
 
 namespace {
@@ -921,27 +929,41 @@ size_t multi_layout(uint32_t T, const sh_params_t *p, size_t *offs)
     return off;
 }
 
+// One batched launch. n_ops bounds the op arrays; work_ops (the ops the descriptors actually
+// hold, or n_ops if unknown) sizes the grid and the ops per wavefront.
+sh_status_t launch_multi_raw(const View *d_dir, uint32_t T, const sh_batch_desc_t *d_desc,
+                             uint32_t nb, const uint8_t *d_ops, const uint32_t *d_keys,
+                             const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,
+                             uint64_t n_ops, uint64_t work_ops, int num_cu, uint32_t wpc,
+                             uint32_t ops_per_wave, uint32_t seq, uint32_t flags,
+                             hipStream_t stream)
+{
+    uint32_t C = ops_per_wave;
+    const uint64_t waves = (uint64_t)num_cu * wpc;
+    if (!C) {
+        C = 64;
+        while (C > 8 && 2 * ((work_ops + C - 1) / C) < waves)
+            C >>= 1;
+    }
+    uint64_t w = waves;
+    const uint64_t chunks = (work_ops + C - 1) / C + nb; // at most one partial chunk each
+    if (w > chunks)
+        w = chunks;
+    const uint32_t blocks = (uint32_t)((w + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(multi_kernel, dim3(blocks ? blocks : 1), dim3(kBlock), 0, stream, d_dir,
+                       T, d_desc, nb, n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq,
+                       C, flags);
+    return check_launch();
+}
+
 sh_status_t launch_multi(sh_multi *m, const sh_batch_desc_t *d_desc, uint32_t nb,
                          const uint8_t *d_ops, const uint32_t *d_keys, const uint32_t *d_vals_in,
                          uint32_t *d_vals_out, uint8_t *d_status, uint64_t n_ops,
                          hipStream_t stream)
 {
-    uint32_t C = m->ops_per_wave;
-    const uint64_t waves = (uint64_t)m->num_cu * m->waves_per_cu;
-    if (!C) {
-        C = 64;
-        while (C > 8 && 2 * ((n_ops + C - 1) / C) < waves)
-            C >>= 1;
-    }
-    uint64_t w = waves;
-    const uint64_t chunks = (n_ops + C - 1) / C + nb; // at most one partial chunk each
-    if (w > chunks)
-        w = chunks;
-    const uint32_t blocks = (uint32_t)((w + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(multi_kernel, dim3(blocks ? blocks : 1), dim3(kBlock), 0, stream,
-                       m->d_dir, m->T, d_desc, nb, n_ops, d_ops, d_keys, d_vals_in, d_vals_out,
-                       d_status, m->seq++, C, m->flags);
-    return check_launch();
+    return launch_multi_raw(m->d_dir, m->T, d_desc, nb, d_ops, d_keys, d_vals_in, d_vals_out,
+                            d_status, n_ops, n_ops, m->num_cu, m->waves_per_cu, m->ops_per_wave,
+                            m->seq++, m->flags, stream);
 }
 
 } // namespace
@@ -1314,6 +1336,386 @@ const char *sh_strerror(sh_status_t s)
         return "busy";
     }
     return "unknown status";
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Served form: a native request loop doing continuous batching (see include/slabhash.h).
+
+namespace {
+
+constexpr uint32_t kMaxLaunches = 8;
+constexpr size_t kCounterBytes = (size_t)kCounterSlots * 8 * sizeof(unsigned long long);
+
+uint64_t clock_now_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct ServerReq {
+    sh_request_t r;
+    uint64_t t_admit;
+    uint64_t t_done; // 0 = not finished (guarded by the server mutex)
+};
+
+struct LaunchSlot {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    sh_batch_desc_t *h_desc = nullptr;   // pinned staging for this launch's descriptors
+    unsigned long long *h_cnt = nullptr; // pinned copy of the table's counter slots
+    sh_batch_desc_t *d_desc = nullptr;   // in the caller's scratch
+    std::vector<uint64_t> tickets;
+    bool busy = false;
+};
+
+} // namespace
+
+struct sh_server {
+    sh_table *t = nullptr;
+    sh_server_cfg_t cfg{};
+    const uint8_t *ops = nullptr;
+    const uint32_t *keys = nullptr, *vals = nullptr;
+    uint32_t *vout = nullptr;
+    uint8_t *sout = nullptr;
+    uint64_t n_ops = 0;
+    View *d_dir = nullptr;
+    int device = 0;
+    LaunchSlot slots[kMaxLaunches];
+    uint32_t nslots = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<ServerReq> reqs;   // indexed by ticket
+    std::deque<uint64_t> pending; // admitted, not yet launched
+    uint64_t unfinished = 0;      // admitted, not yet finished
+    int64_t reserved = 0;         // slabs promised to unfinished requests
+    int64_t allocated = 0;        // pool slabs in use, as last read from the device
+    int64_t base_allocated = 0;
+    long long base_net = 0;
+    uint32_t seq = 0;
+    bool stop = false;
+    std::atomic<int> error{0};
+    std::thread thr;
+};
+
+namespace {
+
+long long counters_net(const unsigned long long *cs)
+{
+    long long net = 0; // slabs allocated minus slabs given back after a lost link
+    for (uint32_t k = 0; k < kCounterSlots; ++k)
+        net += (long long)cs[k * 8 + 2] - (long long)cs[k * 8 + 3];
+    return net;
+}
+
+void server_loop(sh_server *s)
+{
+    hipSetDevice(s->device);
+    for (;;) {
+        bool progressed = false, any_busy = false;
+        // completed launches: stamp their requests, release reservations, refresh occupancy
+        for (uint32_t k = 0; k < s->nslots; ++k) {
+            LaunchSlot &L = s->slots[k];
+            if (!L.busy)
+                continue;
+            const hipError_t q = hipEventQuery(L.ev);
+            if (q == hipErrorNotReady) {
+                any_busy = true;
+                continue;
+            }
+            if (q != hipSuccess)
+                s->error.store(1);
+            const uint64_t now = clock_now_ns();
+            const long long net = counters_net(L.h_cnt);
+            std::lock_guard<std::mutex> g(s->mu);
+            for (uint64_t tk : L.tickets) {
+                ServerReq &R = s->reqs[tk];
+                s->reserved -= R.r.inserts;
+                --s->unfinished;
+                R.t_done = now;
+            }
+            const int64_t a = s->base_allocated + (int64_t)(net - s->base_net);
+            if (a > s->allocated)
+                s->allocated = a; // snapshots can lag one another; occupancy only grows
+            L.tickets.clear();
+            L.busy = false;
+            progressed = true;
+        }
+        // free slots take everything admitted and not yet launched
+        for (uint32_t k = 0; k < s->nslots; ++k) {
+            LaunchSlot &L = s->slots[k];
+            if (L.busy)
+                continue;
+            uint32_t nb = 0;
+            uint64_t work = 0;
+            {
+                std::lock_guard<std::mutex> g(s->mu);
+                while (!s->pending.empty() && nb < kMaxBatches) {
+                    const ServerReq &R = s->reqs[s->pending.front()];
+                    if (nb > 0 && work + R.r.length > s->cfg.max_batch_ops)
+                        break;
+                    L.h_desc[nb].offset = R.r.offset;
+                    L.h_desc[nb].length = R.r.length;
+                    L.h_desc[nb].table = 0;
+                    L.tickets.push_back(s->pending.front());
+                    s->pending.pop_front();
+                    work += R.r.length;
+                    ++nb;
+                }
+            }
+            if (nb == 0)
+                break;
+            bool ok = hipMemcpyAsync(L.d_desc, L.h_desc, nb * sizeof(sh_batch_desc_t),
+                                     hipMemcpyHostToDevice, L.stream) == hipSuccess;
+            ok = ok && launch_multi_raw(s->d_dir, 1, L.d_desc, nb, s->ops, s->keys, s->vals,
+                                        s->vout, s->sout, s->n_ops, work, s->t->num_cu,
+                                        s->t->waves_per_cu, s->t->ops_per_wave, s->seq++,
+                                        kFlagCounters, L.stream) == SH_OK;
+            ok = ok && hipMemcpyAsync(L.h_cnt, s->t->v.counters, kCounterBytes,
+                                      hipMemcpyDeviceToHost, L.stream) == hipSuccess;
+            ok = ok && hipEventRecord(L.ev, L.stream) == hipSuccess;
+            if (!ok)
+                s->error.store(1);
+            L.busy = true;
+            any_busy = true;
+            progressed = true;
+        }
+        if (!progressed) {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (s->stop && s->pending.empty() && !any_busy)
+                break;
+            if (!any_busy && s->pending.empty())
+                s->cv.wait_for(lk, std::chrono::microseconds(200));
+            // with launches in flight the loop keeps polling their events
+        }
+    }
+}
+
+void server_free(sh_server *s)
+{
+    for (uint32_t k = 0; k < s->nslots; ++k) {
+        LaunchSlot &L = s->slots[k];
+        if (L.ev)
+            hipEventDestroy(L.ev);
+        if (L.stream)
+            hipStreamDestroy(L.stream);
+        if (L.h_desc)
+            hipHostFree(L.h_desc);
+        if (L.h_cnt)
+            hipHostFree(L.h_cnt);
+    }
+    delete s;
+}
+
+sh_server_cfg_t server_cfg(const sh_server_cfg_t *c)
+{
+    sh_server_cfg_t r{};
+    if (c)
+        r = *c;
+    if (r.max_launches == 0)
+        r.max_launches = 4;
+    if (r.max_batch_ops == 0)
+        r.max_batch_ops = 1u << 20;
+    if (r.max_requests == 0)
+        r.max_requests = 4096;
+    return r;
+}
+
+} // namespace
+
+extern "C" {
+
+uint64_t sh_clock_ns(void) { return clock_now_ns(); }
+
+size_t sh_server_scratch_bytes(const sh_server_cfg_t *cfg)
+{
+    const sh_server_cfg_t c = server_cfg(cfg);
+    if (c.max_launches > kMaxLaunches)
+        return 0;
+    return 256 + (size_t)c.max_launches * kMaxBatches * sizeof(sh_batch_desc_t);
+}
+
+sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uint8_t *d_ops,
+                            const uint32_t *d_keys, const uint32_t *d_vals_in,
+                            uint32_t *d_vals_out, uint8_t *d_status, uint64_t n_ops,
+                            void *d_scratch, size_t scratch_bytes, void *stream,
+                            sh_server_t **out)
+{
+    const sh_server_cfg_t c = server_cfg(cfg);
+    const size_t need = sh_server_scratch_bytes(&c);
+    if (!t || !out || !d_ops || !d_keys || !d_vals_in || !d_vals_out || !d_status ||
+        n_ops == 0 || n_ops >= (1ull << 40) || !d_scratch || need == 0 ||
+        scratch_bytes < need || (reinterpret_cast<uintptr_t>(d_scratch) & 255u))
+        return SH_EINVAL;
+    sh_server *s = new (std::nothrow) sh_server();
+    if (!s)
+        return SH_ENOMEM;
+    s->t = t;
+    s->cfg = c;
+    s->ops = d_ops;
+    s->keys = d_keys;
+    s->vals = d_vals_in;
+    s->vout = d_vals_out;
+    s->sout = d_status;
+    s->n_ops = n_ops;
+    s->d_dir = reinterpret_cast<View *>(d_scratch);
+    char *sc = static_cast<char *>(d_scratch) + 256;
+    sh_status_t st = (hipGetDevice(&s->device) == hipSuccess) ? SH_OK : SH_EHIP;
+    for (uint32_t k = 0; k < c.max_launches && st == SH_OK; ++k) {
+        LaunchSlot &L = s->slots[k];
+        s->nslots = k + 1;
+        L.d_desc = reinterpret_cast<sh_batch_desc_t *>(sc + (size_t)k * kMaxBatches *
+                                                                 sizeof(sh_batch_desc_t));
+        if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&L.h_desc),
+                          kMaxBatches * sizeof(sh_batch_desc_t), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&L.h_cnt), kCounterBytes,
+                          hipHostMallocDefault) != hipSuccess)
+            st = SH_EHIP;
+    }
+    sh_stats_t stt;
+    if (st == SH_OK &&
+        hipMemcpyAsync(s->d_dir, &t->v, sizeof(View), hipMemcpyHostToDevice, S(stream)) !=
+            hipSuccess)
+        st = SH_EHIP;
+    if (st == SH_OK)
+        st = sh_stats(t, &stt, stream); // synchronises `stream`, so the directory copy is done
+    if (st == SH_OK &&
+        (hipMemcpyAsync(s->slots[0].h_cnt, t->v.counters, kCounterBytes, hipMemcpyDeviceToHost,
+                        S(stream)) != hipSuccess ||
+         hipStreamSynchronize(S(stream)) != hipSuccess))
+        st = SH_EHIP;
+    if (st != SH_OK) {
+        server_free(s);
+        return st;
+    }
+    s->base_allocated = (int64_t)stt.pool_allocated;
+    s->allocated = s->base_allocated;
+    s->base_net = counters_net(s->slots[0].h_cnt);
+    s->thr = std::thread(server_loop, s);
+    *out = s;
+    return SH_OK;
+}
+
+sh_status_t sh_server_submit(sh_server_t *s, const sh_request_t *req, uint64_t *ticket)
+{
+    if (!s || !req || !ticket || req->length == 0 || req->offset > s->n_ops ||
+        req->length > s->n_ops - req->offset || req->inserts > req->length)
+        return SH_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop)
+        return SH_EINVAL;
+    const int64_t avail =
+        (int64_t)s->t->p.pool_slabs - s->allocated - (int64_t)s->cfg.reserve_slabs;
+    if ((int64_t)req->inserts > avail)
+        return s->unfinished == 0 ? SH_ENOMEM : SH_EBUSY;
+    if (s->unfinished >= s->cfg.max_requests || (int64_t)req->inserts > avail - s->reserved)
+        return SH_EBUSY;
+    s->reserved += req->inserts;
+    ++s->unfinished;
+    s->reqs.emplace_back();
+    ServerReq &R = s->reqs.back();
+    R.r = *req;
+    R.t_admit = clock_now_ns();
+    R.t_done = 0;
+    *ticket = s->reqs.size() - 1;
+    s->pending.push_back(*ticket);
+    s->cv.notify_one();
+    return SH_OK;
+}
+
+sh_status_t sh_server_poll(sh_server_t *s, uint64_t ticket, int *done, uint64_t *t_admit_ns,
+                           uint64_t *t_done_ns)
+{
+    if (!s || !done)
+        return SH_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (ticket >= s->reqs.size())
+        return SH_EINVAL;
+    const ServerReq &R = s->reqs[ticket];
+    *done = R.t_done != 0;
+    if (t_admit_ns)
+        *t_admit_ns = R.t_admit;
+    if (t_done_ns)
+        *t_done_ns = R.t_done;
+    return s->error.load() ? SH_EHIP : SH_OK;
+}
+
+sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
+                             const uint64_t *h_arrival_ns, uint64_t n, uint64_t *h_admit_ns,
+                             uint64_t *h_done_ns)
+{
+    if (!s || (n && (!h_reqs || !h_arrival_ns || !h_admit_ns || !h_done_ns)))
+        return SH_EINVAL;
+    for (uint64_t i = 1; i < n; ++i)
+        if (h_arrival_ns[i] < h_arrival_ns[i - 1])
+            return SH_EINVAL;
+    std::vector<uint64_t> ticket(n, UINT64_MAX);
+    std::vector<uint64_t> outstanding;
+    std::deque<uint64_t> backlog;
+    uint64_t next = 0, finished = 0;
+    const uint64_t t0 = clock_now_ns();
+    while (finished < n) {
+        const uint64_t now = clock_now_ns() - t0;
+        while (next < n && h_arrival_ns[next] <= now)
+            backlog.push_back(next++);
+        while (!backlog.empty()) {
+            const uint64_t i = backlog.front();
+            uint64_t tk = 0;
+            const sh_status_t st = sh_server_submit(s, &h_reqs[i], &tk);
+            if (st == SH_EBUSY)
+                break;
+            backlog.pop_front();
+            if (st == SH_OK) {
+                ticket[i] = tk;
+                h_admit_ns[i] = clock_now_ns() - t0;
+                outstanding.push_back(i);
+            } else if (st == SH_ENOMEM) {
+                h_admit_ns[i] = h_done_ns[i] = UINT64_MAX;
+                ++finished;
+            } else {
+                return st;
+            }
+        }
+        if (!outstanding.empty()) {
+            std::lock_guard<std::mutex> g(s->mu);
+            for (size_t j = 0; j < outstanding.size();) {
+                const uint64_t i = outstanding[j];
+                const uint64_t td = s->reqs[ticket[i]].t_done;
+                if (td) {
+                    h_done_ns[i] = td - t0;
+                    ++finished;
+                    outstanding[j] = outstanding.back();
+                    outstanding.pop_back();
+                } else {
+                    ++j;
+                }
+            }
+        }
+        if (s->error.load())
+            return SH_EHIP;
+    }
+    return SH_OK;
+}
+
+sh_status_t sh_server_stop(sh_server_t *s)
+{
+    if (!s)
+        return SH_EINVAL;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_one();
+    if (s->thr.joinable())
+        s->thr.join();
+    const int err = s->error.load();
+    server_free(s);
+    return err ? SH_EHIP : SH_OK;
 }
 
 } // extern "C"

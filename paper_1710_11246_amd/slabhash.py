@@ -56,6 +56,17 @@ class ShStats(ctypes.Structure):
                 ("link_lost", ctypes.c_uint64), ("block_moves", ctypes.c_uint64)]
 
 
+class ShServerCfg(ctypes.Structure):
+    _fields_ = [("max_launches", ctypes.c_uint32), ("max_batch_ops", ctypes.c_uint32),
+                ("max_requests", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("reserve_slabs", ctypes.c_uint64)]
+
+
+class ShRequest(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_uint64), ("length", ctypes.c_uint32),
+                ("inserts", ctypes.c_uint32)]
+
+
 class SlabHashError(RuntimeError):
     def __init__(self, fn: str, code: int):
         super().__init__("%s failed: %s (%d)" % (fn, sh_strerror(code), code))
@@ -84,6 +95,13 @@ _SIGS = {
     "sh_multi_mixed": ([_P, _P, _U32, _P, _P, _P, _P, _P, _U64, _P], ctypes.c_int),
     "sh_multi_graph": ([_P, _P, _U32, _P, _P, _P, _P, _P, _U64, _P], ctypes.c_int),
     "sh_multi_mixed_each": ([_P, _P, _U32, _P, _P, _P, _P, _P, _U64, _P], ctypes.c_int),
+    "sh_server_scratch_bytes": ([_P], _SZ),
+    "sh_server_start": ([_P, _P, _P, _P, _P, _P, _P, _U64, _P, _SZ, _P, _P], ctypes.c_int),
+    "sh_server_submit": ([_P, _P, _P], ctypes.c_int),
+    "sh_server_poll": ([_P, _U64, _P, _P, _P], ctypes.c_int),
+    "sh_server_replay": ([_P, _P, _P, _U64, _P, _P], ctypes.c_int),
+    "sh_server_stop": ([_P], ctypes.c_int),
+    "sh_clock_ns": ([], _U64),
     "sh_graph_launch": ([_P, _P], ctypes.c_int),
     "sh_graph_destroy": ([_P], ctypes.c_int),
     "sh_multi_destroy": ([_P], ctypes.c_int),
@@ -318,6 +336,67 @@ def sh_multi_destroy(m) -> None:
     _check("sh_multi_destroy", lib().sh_multi_destroy(m))
 
 
+# ---------------------------------------------------------------------------------------------
+# Served form
+
+def sh_server_scratch_bytes(cfg: ShServerCfg | None = None) -> int:
+    return int(lib().sh_server_scratch_bytes(ctypes.byref(cfg) if cfg is not None else None))
+
+
+def sh_server_start(t, cfg, ops, keys, vals_in, vals_out, status, scratch: torch.Tensor,
+                    stream=None) -> ctypes.c_void_p:
+    n = keys.numel()
+    out = ctypes.c_void_p()
+    _check("sh_server_start", lib().sh_server_start(
+        t, ctypes.byref(cfg) if cfg is not None else None, _dev(ops, "ops", (torch.uint8,), n),
+        _dev(keys, "keys", _U32_TYPES), _dev(vals_in, "vals_in", _U32_TYPES, n),
+        _dev(vals_out, "vals_out", _U32_TYPES, n), _dev(status, "status", (torch.uint8,), n), n,
+        _dev(scratch, "scratch", (torch.uint8,)), scratch.numel(), _stream(stream),
+        ctypes.byref(out)))
+    return out
+
+
+def sh_server_submit(srv, offset: int, length: int, inserts: int):
+    """Returns (status code, ticket): SH_OK, SH_EBUSY or SH_ENOMEM are returned, not raised."""
+    req = ShRequest(int(offset), int(length), int(inserts))
+    tk = ctypes.c_uint64()
+    code = lib().sh_server_submit(srv, ctypes.byref(req), ctypes.byref(tk))
+    if code not in (SH_OK, SH_EBUSY, SH_ENOMEM):
+        raise SlabHashError("sh_server_submit", code)
+    return code, int(tk.value)
+
+
+def sh_server_poll(srv, ticket: int):
+    """Returns (done, t_admit_ns, t_done_ns)."""
+    d = ctypes.c_int()
+    ta, td = ctypes.c_uint64(), ctypes.c_uint64()
+    _check("sh_server_poll", lib().sh_server_poll(srv, int(ticket), ctypes.byref(d),
+                                                  ctypes.byref(ta), ctypes.byref(td)))
+    return bool(d.value), int(ta.value), int(td.value)
+
+
+def sh_server_replay(srv, offsets, lengths, inserts, arrival_ns):
+    """Submit request i (ops [offsets[i], offsets[i] + lengths[i])) at arrival_ns[i] after the
+    call's start. Returns (admit_ns, done_ns) arrays relative to that start."""
+    n = len(offsets)
+    reqs = np.zeros(n, dtype=[("offset", "<u8"), ("length", "<u4"), ("inserts", "<u4")])
+    reqs["offset"], reqs["length"], reqs["inserts"] = offsets, lengths, inserts
+    arr = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+    adm = np.zeros(n, dtype=np.uint64)
+    done = np.zeros(n, dtype=np.uint64)
+    _check("sh_server_replay", lib().sh_server_replay(srv, reqs.ctypes.data, arr.ctypes.data, n,
+                                                      adm.ctypes.data, done.ctypes.data))
+    return adm, done
+
+
+def sh_server_stop(srv) -> None:
+    _check("sh_server_stop", lib().sh_server_stop(srv))
+
+
+def sh_clock_ns() -> int:
+    return int(lib().sh_clock_ns())
+
+
 def pack_batch_descs(offsets, lengths, tables) -> np.ndarray:
     """sh_batch_desc_t records {uint64 offset; uint32 length; uint32 table} as int64 pairs."""
     off = np.asarray(offsets, dtype=np.uint64)
@@ -473,3 +552,50 @@ class MultiSlabHash:
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
         sh_multi_mixed(self.handle, desc, nb, ops, keys, vals, vo, st, stream)
         return vo, st
+
+
+class Server:
+    """A running server on `table` over device op arrays; stop() (or leaving a with-block)
+    finishes all admitted work."""
+
+    def __init__(self, table: SlabHash, ops, keys, vals, max_launches=0, max_batch_ops=0,
+                 max_requests=0, reserve_slabs=0, stream=None):
+        self.cfg = ShServerCfg(int(max_launches), int(max_batch_ops), int(max_requests), 0,
+                               int(reserve_slabs))
+        self.table = table
+        self.ops, self.keys, self.vals = ops, keys, vals
+        self.vals_out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+        self.status = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        nbytes = sh_server_scratch_bytes(self.cfg)
+        if nbytes == 0:
+            raise ValueError("invalid server configuration")
+        self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=keys.device)
+        torch.cuda.synchronize()
+        self.handle = sh_server_start(table.handle, self.cfg, ops, keys, vals, self.vals_out,
+                                      self.status, self.scratch, stream)
+
+    def submit(self, offset, length, inserts):
+        return sh_server_submit(self.handle, offset, length, inserts)
+
+    def poll(self, ticket):
+        return sh_server_poll(self.handle, ticket)
+
+    def replay(self, offsets, lengths, inserts, arrival_ns):
+        return sh_server_replay(self.handle, offsets, lengths, inserts, arrival_ns)
+
+    def stop(self):
+        if self.handle is not None:
+            h, self.handle = self.handle, None
+            sh_server_stop(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

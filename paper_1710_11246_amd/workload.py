@@ -337,3 +337,87 @@ def multi_rounds(seed: int, T: int, n_lo: int, n_hi: int, len_lo: int, len_hi: i
         R_off.append(np.asarray(offs, dtype=np.int64))
         R_len.append(np.asarray(lns, dtype=np.int64))
     return MultiRounds(seed, ha, hb, init_keys, init_vals, R_ops, R_keys, R_vals, R_off, R_len, occ)
+
+
+@dataclass
+class ServedRequests:
+    """Requests for a served table: request i is ops [offsets[i], offsets[i] + lengths[i]) of
+    the concatenated arrays; inserts[i] counts its insert ops."""
+    ops: np.ndarray
+    keys: np.ndarray
+    vals: np.ndarray
+    offsets: np.ndarray
+    lengths: np.ndarray
+    inserts: np.ndarray
+    mutator: dict = field(default_factory=dict)  # key -> index of the request mutating it
+
+
+def served_requests(seed: int, initial: np.ndarray, n_req: int, len_lo: int, len_hi: int,
+                    fractions=(0.10, 0.05, 0.85), zipf_s: float | None = 1.1,
+                    disjoint: bool = False, absent_frac: float = 0.0) -> ServedRequests:
+    """n_req requests with lengths log-uniform in [len_lo, len_hi] and i.i.d. op kinds with
+    probabilities fractions = (insert, delete, search). Inserts use fresh keys (each once over
+    all requests); deletes use distinct initial keys (each at most once over all requests);
+    searches draw initial keys, Zipf(zipf_s) over a seeded ranking (uniform if zipf_s is None),
+    plus a fraction `absent_frac` of never-inserted keys. With `disjoint`, request i only
+    touches initial keys of its own slice of the initial set (no key is shared between
+    requests)."""
+    rng = SplitMix64(seed)
+    initial = np.asarray(initial, dtype=np.uint32)
+    lens = log_uniform_ints(rng, n_req, len_lo, len_hi)
+    total = int(lens.sum())
+    u = rng.uniform(total)
+    kind = np.where(u < fractions[0], OP_INSERT,
+                    np.where(u < fractions[0] + fractions[1], OP_DELETE, OP_SEARCH)).astype(
+        np.uint8)
+    n_ins = int((kind == OP_INSERT).sum())
+    n_srch = int((kind == OP_SEARCH).sum())
+    fresh = unique_keys(rng, n_ins + n_srch + 16, exclude=initial)
+    keys = np.empty(total, dtype=np.uint32)
+    keys[kind == OP_INSERT] = fresh[:n_ins]
+    absent = fresh[n_ins:]
+    offsets = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    rank_key = initial[rng.permutation(initial.size)]
+    if disjoint:
+        per = initial.size // n_req
+        assert per >= 1, "not enough initial keys for disjoint requests"
+        for i in range(n_req):
+            a, n = int(offsets[i]), int(lens[i])
+            own = rank_key[i * per:(i + 1) * per]
+            k = kind[a:a + n]
+            d = np.flatnonzero(k == OP_DELETE)
+            if d.size > own.size:          # not enough own keys to delete: search instead
+                kind[a + d[own.size:]] = OP_SEARCH
+                d = d[:own.size]
+            dk = own[sample_distinct(rng, d.size, own.size)] if d.size else own[:0]
+            keys[a + d] = dk
+            s_idx = np.flatnonzero(kind[a:a + n] == OP_SEARCH)
+            keys[a + s_idx] = own[rng.below(s_idx.size, own.size)] if s_idx.size else keys[:0]
+    else:
+        d = np.flatnonzero(kind == OP_DELETE)
+        if d.size > initial.size:
+            kind[d[initial.size:]] = OP_SEARCH
+            d = d[:initial.size]
+        keys[d] = rank_key[sample_distinct(rng, d.size, initial.size)]
+        s_idx = np.flatnonzero(kind == OP_SEARCH)
+        if zipf_s is None:
+            keys[s_idx] = rank_key[rng.below(s_idx.size, rank_key.size)]
+        else:
+            keys[s_idx] = rank_key[zipf_ranks(rng, s_idx.size, rank_key.size, zipf_s) - 1]
+    if absent_frac > 0:
+        s_idx = np.flatnonzero(kind == OP_SEARCH)
+        pick = s_idx[rng.uniform(s_idx.size) < absent_frac]
+        keys[pick] = absent[rng.below(pick.size, absent.size)] if pick.size else keys[:0]
+    vals = value_of(keys) ^ np.uint32(0x9E3779B9)
+    ins_per = np.add.reduceat((kind == OP_INSERT).astype(np.int64), offsets) if total else \
+        np.zeros(n_req, np.int64)
+    mut = np.flatnonzero(kind != OP_SEARCH)
+    req_of = np.searchsorted(offsets, mut, side="right") - 1
+    mutator = dict(zip(keys[mut].tolist(), req_of.tolist()))
+    return ServedRequests(kind, keys, vals, offsets, lens.astype(np.int64), ins_per, mutator)
+
+
+def poisson_arrivals(rng: SplitMix64, n: int, rate_per_s: float) -> np.ndarray:
+    """Arrival times (ns, from 0) of a Poisson process with the given rate."""
+    gaps = -np.log1p(-rng.uniform(n)) / rate_per_s
+    return np.round(np.cumsum(gaps) * 1e9).astype(np.uint64)

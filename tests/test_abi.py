@@ -99,3 +99,20 @@ def test_multi_argument_errors(lib):
     assert int.from_bytes(bytes(d[1, :8]), "little") == 7
     assert int.from_bytes(bytes(d[1, 8:12]), "little") == 3
     assert int.from_bytes(bytes(d[1, 12:16]), "little") == 2
+
+
+def test_server_argument_errors(lib):
+    assert S.sh_server_scratch_bytes() == 256 + 4 * 4096 * 16
+    assert S.sh_server_scratch_bytes(S.ShServerCfg(8, 0, 0, 0, 0)) == 256 + 8 * 4096 * 16
+    assert S.sh_server_scratch_bytes(S.ShServerCfg(9, 0, 0, 0, 0)) == 0
+    out = ctypes.c_void_p()
+    assert lib.sh_server_start(None, None, 256, 256, 256, 256, 256, 10, 256, 1 << 20, None,
+                               ctypes.byref(out)) == S.SH_EINVAL
+    req = S.ShRequest(0, 1, 0)
+    tk = ctypes.c_uint64()
+    assert lib.sh_server_submit(None, ctypes.byref(req), ctypes.byref(tk)) == S.SH_EINVAL
+    assert lib.sh_server_poll(None, 0, None, None, None) == S.SH_EINVAL
+    assert lib.sh_server_replay(None, None, None, 0, None, None) == S.SH_EINVAL
+    assert lib.sh_server_stop(None) == S.SH_EINVAL
+    a, b = S.sh_clock_ns(), S.sh_clock_ns()
+    assert 0 < a <= b

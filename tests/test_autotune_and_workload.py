@@ -84,3 +84,37 @@ def test_multi_rounds_generator_properties(n_lo, len_hi):
                                                       mr.lengths[r][t]] == 1).sum())
                                           for r in range(4)) for t in range(12)]
     assert list(mr.final_occupancy) == occ
+
+
+def test_zipf_ranks_match_distribution():
+    from scipy.stats import chisquare
+    num, s, n = 50, 1.1, 400000
+    r = W.zipf_ranks(W.SplitMix64(3), n, num, s)
+    assert r.min() >= 1 and r.max() <= num
+    w = np.arange(1, num + 1, dtype=float) ** -s
+    expect = n * w / w.sum()
+    obs = np.bincount(r, minlength=num + 1)[1:]
+    assert chisquare(obs, expect).pvalue > 1e-4
+
+
+def test_served_requests_properties():
+    init = W.unique_keys(W.SplitMix64(1), 5000)
+    sr = W.served_requests(7, init, 60, 1, 500, zipf_s=1.1)
+    assert sr.lengths.sum() == sr.keys.size and (sr.lengths >= 1).all()
+    mut = sr.ops != W.OP_SEARCH
+    assert np.unique(sr.keys[mut]).size == int(mut.sum())   # each key mutated at most once
+    ins = sr.keys[sr.ops == W.OP_INSERT]
+    assert not np.isin(ins, init).any()
+    assert np.isin(sr.keys[sr.ops == W.OP_DELETE], init).all()
+    for i in range(60):
+        a, n = sr.offsets[i], sr.lengths[i]
+        assert sr.inserts[i] == int((sr.ops[a:a + n] == W.OP_INSERT).sum())
+    d = W.served_requests(8, init, 40, 1, 100, zipf_s=None, disjoint=True)
+    owner = {}
+    for i in range(40):
+        a, n = d.offsets[i], d.lengths[i]
+        for k in d.keys[a:a + n][d.ops[a:a + n] != W.OP_INSERT].tolist():
+            assert owner.setdefault(k, i) == i               # no initial key shared
+    arr = W.poisson_arrivals(W.SplitMix64(2), 20000, 1e6)
+    assert (np.diff(arr.astype(np.int64)) >= 0).all()
+    assert abs(arr[-1] / 1e9 - 20000 / 1e6) < 0.05 * 20000 / 1e6
