@@ -214,6 +214,100 @@ def run_batched(seed: int = 31, T: int = 256, rounds: int = 20, wpc_override: in
     return res
 
 
+def run_served(seed: int = 41, n_keys: int = 1 << 26, n_req: int = 10000,
+               loads=(0.5, 0.8, 0.95)):
+    """Served workload: a resident table of n_keys uint32 keys (buckets from the autotuner for
+    utilisation 0.6, pool sized for the run's inserts) receiving n_req requests, each a mixed
+    batch of log-uniform length in [1, 2^16] with i.i.d. ops 10% insert (fresh keys) / 5%
+    delete (initial keys, each at most once) / 85% search (Zipf s = 1.1 over the initial keys).
+    The plain path's capacity is measured by running every request as its own sh_mixed launch,
+    back to back; the server's by submitting all requests at once. Poisson arrivals at each
+    offered load (a fraction of the plain capacity, then of the server's) give p50/p99 latency
+    (completion minus arrival, including time waiting for admission) and throughput. The table
+    is rebuilt before each run."""
+    import torch
+    from paper_1710_11246_amd import autotune as A
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    t0 = time.perf_counter()
+    rng = W.SplitMix64(seed)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    init = W.distinct_keys(seed, 0, n_keys)
+    fresh = W.distinct_keys(seed, n_keys, n_keys // 4)  # disjoint from init by construction
+    sr = W.served_requests(seed + 1, init, n_req, 1, 1 << 16, fractions=(0.10, 0.05, 0.85),
+                           zipf_s=1.1, shuffle_ranking=False, fresh_keys=fresh)
+    n_final = n_keys + int(sr.inserts.sum())
+    B = A.buckets_for_utilisation(n_final, 0.6)
+    # Admission promises each request its worst case (a new slab per insert), so beyond the
+    # expected overflow the pool carries 2^20 slabs (256 MB) of headroom for those promises.
+    params = [S.ShParams(B, A.pool_slabs_for(n_final, B) + (1 << 20), a, b)]
+    log("served inputs: %d keys, %d requests, %d ops (%.1f s)" % (
+        n_keys, n_req, sr.keys.size, time.perf_counter() - t0))
+    m = S.MultiSlabHash(params)
+    tb = m.tables[0]
+    kd, vd = S.to_dev(init), S.to_dev(W.value_of(init))
+    ops, keys, vals = S.to_dev(sr.ops), S.to_dev(sr.keys), S.to_dev(sr.vals)
+    vout = torch.empty(keys.numel(), dtype=torch.int32, device="cuda")
+    sout = torch.empty(keys.numel(), dtype=torch.uint8, device="cuda")
+    n_ops = int(sr.keys.size)
+    mean_len = n_ops / n_req
+
+    def rebuild():
+        tb.reset()
+        S.sh_build(tb.handle, kd, vd, None)
+        torch.cuda.synchronize()
+
+    rebuild()
+    st0 = tb.stats()
+    h_desc = S.pack_batch_descs(sr.offsets, sr.lengths, np.zeros(n_req, np.int64))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    S.sh_multi_mixed_each(m.handle, h_desc, ops, keys, vals, vout, sout)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t
+    cap_plain = n_ops / plain_s
+
+    def serve(arrivals):
+        rebuild()
+        with S.Server(tb, ops, keys, vals) as srv:
+            adm, done = srv.replay(sr.offsets, sr.lengths, sr.inserts, arrivals)
+            srv.stop()
+        ok = done != np.iinfo(np.uint64).max
+        lat = (done[ok].astype(np.int64) - arrivals[ok].astype(np.int64)) / 1e3  # us
+        span = (int(done[ok].max()) - int(arrivals.min())) / 1e9
+        return {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                "p99_us": round(float(np.percentile(lat, 99)), 1),
+                "mean_us": round(float(lat.mean()), 1),
+                "Mops": round(float(sr.lengths[ok].sum()) / span / 1e6, 1),
+                "rejected": int((~ok).sum())}
+
+    closed = serve(np.zeros(n_req, np.uint64))
+    cap_served = closed["Mops"] * 1e6
+    points = []
+    for ref, cap in (("plain", cap_plain), ("served", cap_served)):
+        for load in loads:
+            rate = load * cap / mean_len
+            arr = W.poisson_arrivals(W.SplitMix64(seed + 7), n_req, rate)
+            r = serve(arr)
+            r.update({"offered_load": load, "of_capacity": ref,
+                      "offered_Mops": round(load * cap / 1e6, 1),
+                      "arrival_rate_per_s": round(rate, 1)})
+            points.append(r)
+    s_end = tb.stats()
+    return {
+        "workload": "resident 2^26-key table, %d requests of log-uniform length [1, 2^16], "
+                    "10/5/85 insert/delete/search, Zipf 1.1 searches, Poisson arrivals" % n_req,
+        "keys": n_keys, "num_buckets": B, "pool_slabs": params[0].pool_slabs,
+        "ops": n_ops, "mean_request_ops": round(mean_len, 1),
+        "utilisation_start": round(8.0 * st0["live"] / (256.0 * st0["slabs_total"]), 4),
+        "plain_capacity_Mops": round(cap_plain / 1e6, 1),
+        "served_closed_loop": closed,
+        "served_closed_loop_vs_plain": round(closed["Mops"] * 1e6 / cap_plain, 2),
+        "load_points": points,
+        "violations_end": s_end["violations"], "error_word_end": s_end["error_word"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +319,7 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="also time build/search at every utilisation target")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form section")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-form section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device once (a reference "
                          "for scaling hardware traffic counters)")
@@ -392,6 +487,12 @@ def main():
         log("batched form")
         batched = run_batched()
 
+    served = None
+    if not args.no_served:
+        torch.cuda.empty_cache()
+        log("served form")
+        served = run_served()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -428,6 +529,8 @@ def main():
         out["sweep"] = sweep
     if batched is not None:
         out["batched"] = batched
+    if served is not None:
+        out["served"] = served
     print(json.dumps(out), flush=True)
 
 

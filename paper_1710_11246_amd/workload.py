@@ -42,10 +42,15 @@ class SplitMix64:
         self.count = 0
 
     def next(self, n: int) -> np.ndarray:
-        idx = np.arange(self.count + 1, self.count + 1 + n, dtype=np.uint64)
-        self.count += n
+        out = np.empty(n, dtype=np.uint64)
+        step = 1 << 22  # chunks keep the temporaries in cache
         with np.errstate(over="ignore"):
-            return splitmix64_mix(self.seed + idx * GOLDEN)
+            for a in range(0, n, step):
+                b = min(n, a + step)
+                idx = np.arange(self.count + 1 + a, self.count + 1 + b, dtype=np.uint64)
+                out[a:b] = splitmix64_mix(self.seed + idx * GOLDEN)
+        self.count += n
+        return out
 
     def uniform(self, n: int) -> np.ndarray:
         """n doubles in [0, 1) from the top 53 bits."""
@@ -87,6 +92,36 @@ def unique_keys(rng: SplitMix64, n: int, exclude: np.ndarray | None = None) -> n
     return out[:n].copy()
 
 
+def _fmix32(h: np.ndarray) -> np.ndarray:
+    """MurmurHash3's 32-bit finaliser (Appleby), a bijection of the 32-bit integers."""
+    h = h ^ (h >> np.uint32(16))
+    h = h * np.uint32(0x85EBCA6B)
+    h = h ^ (h >> np.uint32(13))
+    h = h * np.uint32(0xC2B2AE35)
+    return h ^ (h >> np.uint32(16))
+
+
+def _perm32(seed: int, x: np.ndarray) -> np.ndarray:
+    s = splitmix64_mix(np.array([seed], dtype=np.uint64))[0]
+    s1, s2 = np.uint32(int(s) & 0xFFFFFFFF), np.uint32(int(s) >> 32)
+    with np.errstate(over="ignore"):
+        return _fmix32(_fmix32(x ^ s1) ^ s2)
+
+
+def distinct_keys(seed: int, start: int, n: int) -> np.ndarray:
+    """n distinct keys: a seeded bijection of the 32-bit integers applied to the counters
+    start, start + 1, ..., so calls with non-overlapping counter ranges (and the same seed)
+    give disjoint key sets; no sorting is needed. The reserved key is replaced by the image of
+    counter 2^32 - 1, which no range below it uses."""
+    assert 0 <= start and start + n < 0xFFFFFFFF
+    x = np.arange(start, start + n, dtype=np.uint64).astype(np.uint32)
+    k = _perm32(seed, x)
+    bad = k == np.uint32(RESERVED_KEY)
+    if bad.any():
+        k[bad] = _perm32(seed, np.array([0xFFFFFFFF], dtype=np.uint32))[0]
+    return k
+
+
 def log_uniform_ints(rng: SplitMix64, n: int, lo: int, hi: int) -> np.ndarray:
     """n integers, log-uniform on [lo, hi]: floor(exp(ln lo + U (ln(hi+1) - ln lo)))."""
     u = rng.uniform(n)
@@ -120,7 +155,7 @@ def zipf_ranks(rng: SplitMix64, n: int, num: int, s: float) -> np.ndarray:
     out = np.empty(n, dtype=np.int64)
     filled = 0
     while filled < n:
-        m = (n - filled) * 2 + 64
+        m = (n - filled) + (n - filled) // 8 + 64  # acceptance is above 0.9 for s > 1
         u = h_n + rng.uniform(m) * (h_x1 - h_n)
         x = Hinv(u)
         k = np.clip(np.floor(x + 0.5), 1, num)
@@ -349,19 +384,29 @@ class ServedRequests:
     offsets: np.ndarray
     lengths: np.ndarray
     inserts: np.ndarray
-    mutator: dict = field(default_factory=dict)  # key -> index of the request mutating it
+    mut_keys: np.ndarray = None  # keys some request mutates (each exactly once)
+    mut_req: np.ndarray = None   # the request mutating mut_keys[i]
+
+    @property
+    def mutator(self) -> dict:
+        """key -> index of the request that mutates it."""
+        return dict(zip(self.mut_keys.tolist(), self.mut_req.tolist()))
 
 
 def served_requests(seed: int, initial: np.ndarray, n_req: int, len_lo: int, len_hi: int,
                     fractions=(0.10, 0.05, 0.85), zipf_s: float | None = 1.1,
-                    disjoint: bool = False, absent_frac: float = 0.0) -> ServedRequests:
+                    disjoint: bool = False, absent_frac: float = 0.0,
+                    shuffle_ranking: bool = True,
+                    fresh_keys: np.ndarray | None = None) -> ServedRequests:
     """n_req requests with lengths log-uniform in [len_lo, len_hi] and i.i.d. op kinds with
     probabilities fractions = (insert, delete, search). Inserts use fresh keys (each once over
     all requests); deletes use distinct initial keys (each at most once over all requests);
     searches draw initial keys, Zipf(zipf_s) over a seeded ranking (uniform if zipf_s is None),
     plus a fraction `absent_frac` of never-inserted keys. With `disjoint`, request i only
     touches initial keys of its own slice of the initial set (no key is shared between
-    requests)."""
+    requests). Without `shuffle_ranking` the initial keys' own order (their random draw order)
+    serves as the Zipf ranking, which saves a sort for very large tables. `fresh_keys`, if
+    given, supplies keys known to be absent from `initial` (inserts, then absent searches)."""
     rng = SplitMix64(seed)
     initial = np.asarray(initial, dtype=np.uint32)
     lens = log_uniform_ints(rng, n_req, len_lo, len_hi)
@@ -372,12 +417,17 @@ def served_requests(seed: int, initial: np.ndarray, n_req: int, len_lo: int, len
         np.uint8)
     n_ins = int((kind == OP_INSERT).sum())
     n_srch = int((kind == OP_SEARCH).sum())
-    fresh = unique_keys(rng, n_ins + n_srch + 16, exclude=initial)
+    n_fresh = n_ins + (n_srch + 16 if absent_frac > 0 else 0)
+    if fresh_keys is not None:
+        assert fresh_keys.size >= n_fresh
+        fresh = np.asarray(fresh_keys[:n_fresh], dtype=np.uint32)
+    else:
+        fresh = unique_keys(rng, n_fresh, exclude=initial)
     keys = np.empty(total, dtype=np.uint32)
     keys[kind == OP_INSERT] = fresh[:n_ins]
     absent = fresh[n_ins:]
     offsets = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
-    rank_key = initial[rng.permutation(initial.size)]
+    rank_key = initial[rng.permutation(initial.size)] if shuffle_ranking else initial
     if disjoint:
         per = initial.size // n_req
         assert per >= 1, "not enough initial keys for disjoint requests"
@@ -413,8 +463,8 @@ def served_requests(seed: int, initial: np.ndarray, n_req: int, len_lo: int, len
         np.zeros(n_req, np.int64)
     mut = np.flatnonzero(kind != OP_SEARCH)
     req_of = np.searchsorted(offsets, mut, side="right") - 1
-    mutator = dict(zip(keys[mut].tolist(), req_of.tolist()))
-    return ServedRequests(kind, keys, vals, offsets, lens.astype(np.int64), ins_per, mutator)
+    return ServedRequests(kind, keys, vals, offsets, lens.astype(np.int64), ins_per, keys[mut],
+                          req_of)
 
 
 def poisson_arrivals(rng: SplitMix64, n: int, rate_per_s: float) -> np.ndarray:

@@ -118,3 +118,15 @@ def test_served_requests_properties():
     arr = W.poisson_arrivals(W.SplitMix64(2), 20000, 1e6)
     assert (np.diff(arr.astype(np.int64)) >= 0).all()
     assert abs(arr[-1] / 1e9 - 20000 / 1e6) < 0.05 * 20000 / 1e6
+
+
+def test_distinct_keys_are_distinct_and_disjoint():
+    a = W.distinct_keys(5, 0, 1 << 20)
+    b = W.distinct_keys(5, 1 << 20, 1 << 18)
+    assert np.unique(a).size == a.size and np.unique(b).size == b.size
+    assert not np.isin(b, a).any() and (a != W.RESERVED_KEY).all()
+    assert (W.distinct_keys(5, 7, 10) == a[7:17]).all()          # counter-based
+    assert not (W.distinct_keys(6, 0, 1000) == a[:1000]).all()   # seeded
+    # roughly uniform: the top 4 bits are balanced
+    counts = np.bincount(a >> np.uint32(28), minlength=16)
+    assert counts.min() > 0.9 * a.size / 16
