@@ -41,9 +41,9 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
 # Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
 # a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
-TRAFFIC_SRC_SHA = "abe8f75237fc802b"
-TRAFFIC_BYTES = {"build": 1463722613, "search_hit": 1038286130, "search_miss": 1038286130,
-                 "mixed": 19452702, "reset": 94478514}
+TRAFFIC_SRC_SHA = "07c89a174112b878"
+TRAFFIC_BYTES = {"build": 1464379874, "search_hit": 1038327028, "search_miss": 1038327028,
+                 "mixed": 19445370, "reset": 94466969}
 
 
 def source_sha() -> str:
