@@ -308,6 +308,41 @@ def run_served(seed: int = 41, n_keys: int = 1 << 26, n_req: int = 10000,
     }
 
 
+def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
+    """Ceilings of the operation kernels' memory access patterns, from libslabhash_roofs.so, over
+    a buffer of nbytes (the benchmark table's size): n_ops random 256-byte slab reads (the
+    pattern of a search that finds its key in the base slab), n_ops random 64-bit
+    compare-and-swaps, and n_ops slab reads each followed by a compare-and-swap into the slab
+    (the pattern of an insert). Each is the median of `reps` runs at the faster of two launch
+    shapes; the buffer is refilled with all ones before every run."""
+    import torch
+    from paper_1710_11246_amd import roofs as R
+    buf = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda")
+    res = {"buffer_bytes": buf.numel() * 8, "ops": n_ops}
+    for name, kind in (("slab_load", R.SH_ROOF_SLAB_LOAD), ("cas", R.SH_ROOF_CAS),
+                       ("load_cas", R.SH_ROOF_LOAD_CAS)):
+        best = None
+        for wpc in (16, 32):
+            ts = []
+            for r in range(reps + 1):
+                buf.fill_(-1)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                R.sh_roof_run(kind, buf, n_ops, wpc, seed=17 * r + 1)
+                e1.record()
+                torch.cuda.synchronize()
+                if r:
+                    ts.append(e0.elapsed_time(e1) * 1e3)
+            t = float(np.median(ts))
+            if best is None or t < best[0]:
+                best = (t, wpc)
+        res[name + "_us"] = round(best[0], 1)
+        res[name + "_waves_per_cu"] = best[1]
+    del buf
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,6 +478,21 @@ def main():
             "traffic": TRAFFIC_BYTES[dom] if traffic_ok else None, "kernel": dom,
             "bytes_per_launch": int(bytes_l[dom])}
 
+    log("access-pattern ceilings")
+    patterns = measure_patterns(int(table.storage.numel()), N_KEYS)
+    # each kernel against the ceiling of its own access pattern, measured above
+    pattern_of = {"build": "load_cas", "search_hit": "slab_load", "search_miss": "slab_load"}
+    for k, pat in pattern_of.items():
+        kernels[k]["pattern_ceiling_us"] = patterns[pat + "_us"]
+        kernels[k]["frac_of_pattern_ceiling"] = round(patterns[pat + "_us"] /
+                                                      (avg_ms[k] * 1e3), 4)
+    if dom in pattern_of:
+        roof["secondary"] = {
+            "bound": "atomic" if dom == "build" else "hbm",
+            "pattern": pattern_of[dom], "ceiling_us": patterns[pattern_of[dom] + "_us"],
+            "kernel_us": round(avg_ms[dom] * 1e3, 1),
+            "frac": kernels[dom]["frac_of_pattern_ceiling"]}
+
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
@@ -523,6 +573,7 @@ def main():
         "kernels": kernels,
         "build_counters": build_counters,
         "roofline": roof,
+        "access_patterns": patterns,
         "cpu_baseline": cpu,
     }
     if sweep is not None:

@@ -1,0 +1,51 @@
+/*
+ * slabhash_roofs.h -- microbenchmarks of the memory access patterns the slab hash is made of,
+ * used to measure the ceilings its kernels run against on one GPU. Nothing here touches a table.
+ *
+ * The patterns, each over a buffer of whole 256-byte slabs with slab s of operation i chosen by
+ * a fixed 32-bit mix of (seed + i) scaled into [0, slabs):
+ *   SH_ROOF_SLAB_LOAD  one operation = one 256-byte slab read by half a wavefront, 8 bytes per
+ *                      lane with device-coherent loads; a wavefront reads two slabs per load
+ *                      instruction, as the operation kernels do ("Search": one slab read per
+ *                      operation when the key is in its base slab).
+ *   SH_ROOF_CAS        one operation = one 64-bit compare-and-swap with return, device scope, on
+ *                      a random word of a random slab, expecting all ones (an empty slot); one
+ *                      operation per lane.
+ *   SH_ROOF_LOAD_CAS   one operation = one slab read as in SH_ROOF_SLAB_LOAD, then one 64-bit
+ *                      compare-and-swap on the slab's first all-ones word (slot 0 if none) by
+ *                      the half-wavefront's first lane: the memory pattern of an insert that
+ *                      finds its key absent and an empty slot in its base slab ("Insertion").
+ *
+ * The compare-and-swap patterns overwrite the words they win; fill the buffer with 0xFF bytes
+ * before each timed run so every run starts from empty slots.
+ */
+#ifndef SLABHASH_ROOFS_H
+#define SLABHASH_ROOFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "slabhash.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { SH_ROOF_SLAB_LOAD = 0, SH_ROOF_CAS = 1, SH_ROOF_LOAD_CAS = 2 };
+
+/* Enqueue n_ops operations of pattern `kind` over d_buf on `stream` (a hipStream_t, NULL = the
+   default stream); asynchronous.
+   d_buf:        device buffer, 256-byte aligned, caller-owned.
+   bytes:        a multiple of 256, at least 256, at most (2^32 - 1) * 256.
+   n_ops:        below 2^32; 0 is a no-op.
+   waves_per_cu: persistent grid of waves_per_cu * (compute units) wavefronts, 1..64 (0 = 32).
+   Returns SH_EINVAL for a bad kind or argument (nothing enqueued), SH_EHIP if the device query
+   or the launch fails, else SH_OK. */
+sh_status_t sh_roof_run(int kind, void *d_buf, size_t bytes, uint64_t n_ops,
+                        uint32_t waves_per_cu, uint32_t seed, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,60 @@
+"""ctypes binding of libslabhash_roofs.so (include/slabhash_roofs.h): microbenchmarks of the slab
+hash's memory access patterns, used to measure the ceilings its kernels run against. Argument
+marshalling only; every pattern runs in the library's kernels."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+from .slabhash import SH_OK, SlabHashError, _stream
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libslabhash_roofs.so")
+HEADER_PATH = os.path.join(os.path.dirname(PKG), "include", "slabhash_roofs.h")
+
+SH_ROOF_SLAB_LOAD, SH_ROOF_CAS, SH_ROOF_LOAD_CAS = 0, 1, 2
+
+_SIGS = {
+    "sh_roof_run": ([ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64,
+                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int),
+}
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libslabhash_roofs.so (built by paper_1710_11246_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libslabhash_roofs.so is not built (%s); run "
+                               "`python -m paper_1710_11246_amd.build`" % LIB_PATH)
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(l, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = l
+    return _lib
+
+
+def declared_symbols() -> list[str]:
+    """Entry points declared in include/slabhash_roofs.h."""
+    text = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(sh_\w+)\s*\(", text, re.M)))
+
+
+def sh_roof_run(kind: int, buf: torch.Tensor, n_ops: int, waves_per_cu: int = 0, seed: int = 1,
+                stream=None) -> None:
+    """Enqueue n_ops operations of pattern `kind` over the device tensor `buf` (its bytes,
+    rounded down to whole 256-byte slabs)."""
+    if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.is_contiguous()):
+        raise ValueError("buf must be a contiguous device tensor")
+    nbytes = (buf.numel() * buf.element_size()) // 256 * 256
+    code = lib().sh_roof_run(int(kind), ctypes.c_void_p(buf.data_ptr()), nbytes, int(n_ops),
+                             int(waves_per_cu), int(seed) & 0xFFFFFFFF,
+                             ctypes.c_void_p(_stream(stream)))
+    if code != SH_OK:
+        raise SlabHashError("sh_roof_run", code)

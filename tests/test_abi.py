@@ -116,3 +116,22 @@ def test_server_argument_errors(lib):
     assert lib.sh_server_stop(None) == S.SH_EINVAL
     a, b = S.sh_clock_ns(), S.sh_clock_ns()
     assert 0 < a <= b
+
+
+def test_roofs_library_exports_and_argument_errors():
+    from paper_1710_11246_amd import roofs as R
+    if not os.path.exists(R.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    rl = R.lib()
+    declared = R.declared_symbols()
+    assert declared == ["sh_roof_run"] and set(declared) == set(R._SIGS)
+    assert hasattr(rl, "sh_roof_run")
+    buf = ctypes.c_void_p(1 << 20)  # aligned stand-in; every call below fails before using it
+    bad = [(7, buf, 1 << 20, 10, 0), (-1, buf, 1 << 20, 10, 0), (0, None, 1 << 20, 10, 0),
+           (0, ctypes.c_void_p((1 << 20) + 8), 1 << 20, 10, 0), (0, buf, 100, 10, 0),
+           (0, buf, 300, 10, 0), (0, buf, 1 << 20, 1 << 32, 0), (0, buf, 1 << 20, 10, 65)]
+    for kind, p, nbytes, n, wpc in bad:
+        assert rl.sh_roof_run(kind, p, nbytes, n, wpc, 1, None) == S.SH_EINVAL
+    # no operations: nothing is enqueued and no device is touched
+    assert rl.sh_roof_run(1, buf, 1 << 20, 0, 0, 1, None) == S.SH_OK
