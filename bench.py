@@ -214,6 +214,76 @@ def run_batched(seed: int = 31, T: int = 256, rounds: int = 20, wpc_override: in
     return res
 
 
+def run_concurrent(seed: int = 51, total: int = 1 << 24, batch: int = 1 << 16,
+                   B: int = 793240, per_gamma: int = 16) -> dict:
+    """Concurrent workload ("Incremental insertion" and "Concurrent benchmarks"): one table with
+    B buckets (final utilisation about 0.65 after 2^24 keys) grows by insert-only batches of
+    `batch` fresh keys; when it holds 2^20, 2^22 and 2^24 growth keys, `per_gamma` mixed batches
+    of 2^16 ops run for each of the paper's distributions Gamma0, Gamma1 and Gamma2. Every batch
+    is its own sh_insert or sh_mixed launch, timed with HIP events."""
+    import torch
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    t0 = time.perf_counter()
+    cps = [1 << 20, 1 << 22, 1 << 24]
+    g = W.growth_checkpoints(seed, total, batch, cps, per_gamma, MIX_BATCH, S.SH_HASH_PRIME)
+    log("concurrent inputs: %d growth keys, %d mixed batches (%.1f s)" % (
+        total, sum(len(b) for pc in g.mixed for _, b in pc), time.perf_counter() - t0))
+    pool = S.pool_slabs_bound(total + g.mixed_inserts)
+    t = S.SlabHash(B, pool, g.hash_a, g.hash_b)
+    kd, vd = S.to_dev(g.keys), S.to_dev(g.vals)
+    st = torch.empty(batch, dtype=torch.uint8, device="cuda")
+    vo = torch.empty(MIX_BATCH, dtype=torch.int32, device="cuda")
+    so = torch.empty(MIX_BATCH, dtype=torch.uint8, device="cuda")
+    grown = 0
+    growth_ms = []
+    cp_res = []
+    for cp, per_cp in zip(cps, g.mixed):
+        evs = []
+        for s0 in range(grown, cp, batch):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            S.sh_insert(t.handle, kd[s0:s0 + batch], vd[s0:s0 + batch], st)
+            e1.record()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        growth_ms += [a.elapsed_time(b) for a, b in evs]
+        grown = cp
+        stats = t.stats()
+        r = {"growth_keys": cp,
+             "utilisation": round(8.0 * stats["live"] / (256.0 * stats["slabs_total"]), 4),
+             "insert_batch_Mops_last16": round(
+                 batch * 16 / (sum(growth_ms[-16:]) * 1e-3) / 1e6, 1)}
+        for name, batches in per_cp:
+            dev = [(S.to_dev(o), S.to_dev(k), S.to_dev(v)) for o, k, v in batches]
+            evs = []
+            for o, k, v in dev:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                S.sh_mixed(t.handle, o, k, v, vo, so)
+                e1.record()
+                evs.append((e0, e1))
+            torch.cuda.synchronize()
+            ms = [a.elapsed_time(b) for a, b in evs]
+            r[name + "_Mops"] = round(MIX_BATCH * len(ms) / (sum(ms) * 1e-3) / 1e6, 1)
+        cp_res.append(r)
+        log("  grown to %d: %s" % (cp, r))
+    end = t.stats()
+    return {
+        "workload": "grow to 2^24 uniform keys in insert batches of 2^16 (B=793240, final "
+                    "utilisation ~0.65); at 2^20, 2^22 and 2^24 keys, 16 concurrent batches of "
+                    "2^16 ops for each of Gamma0 (0.5,0.5,0,0), Gamma1 (0.2,0.2,0.3,0.3), "
+                    "Gamma2 (0.1,0.1,0.4,0.4)",
+        "num_buckets": B, "pool_slabs": pool, "insert_batch": batch,
+        "insert_batches": len(growth_ms),
+        "insert_Mops_overall": round(total / (sum(growth_ms) * 1e-3) / 1e6, 1),
+        "checkpoints": cp_res,
+        "violations_end": end["violations"], "error_word_end": end["error_word"],
+    }
+
+
 def run_served(seed: int = 41, n_keys: int = 1 << 26, n_req: int = 10000,
                loads=(0.5, 0.8, 0.95)):
     """Served workload: a resident table of n_keys uint32 keys (buckets from the autotuner for
@@ -355,6 +425,8 @@ def main():
                     help="also time build/search at every utilisation target")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form section")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form section")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the incremental-growth and concurrent-batch section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device once (a reference "
                          "for scaling hardware traffic counters)")
@@ -537,6 +609,12 @@ def main():
         log("batched form")
         batched = run_batched()
 
+    concurrent = None
+    if not args.no_concurrent:
+        torch.cuda.empty_cache()
+        log("concurrent form")
+        concurrent = run_concurrent()
+
     served = None
     if not args.no_served:
         torch.cuda.empty_cache()
@@ -580,6 +658,8 @@ def main():
         out["sweep"] = sweep
     if batched is not None:
         out["batched"] = batched
+    if concurrent is not None:
+        out["concurrent"] = concurrent
     if served is not None:
         out["served"] = served
     print(json.dumps(out), flush=True)

@@ -257,6 +257,72 @@ def gamma_counts(length: int, fractions) -> tuple[int, int, int, int]:
     return n_ins, n_del, n_hit, rest - n_hit
 
 
+#: The paper's three operation distributions of the concurrent benchmark ("Concurrent
+#: benchmarks"): (insert new, delete existing, search existing, search absent).
+GAMMAS = {"gamma0": (0.5, 0.5, 0.0, 0.0), "gamma1": (0.2, 0.2, 0.3, 0.3),
+          "gamma2": (0.1, 0.1, 0.4, 0.4)}
+
+
+@dataclass
+class Growth:
+    """Incremental growth with concurrent batches at checkpoints. The table receives `keys` in
+    insert-only batches of `batch`; when it has received checkpoints[c] of them, the batches of
+    mixed[c] run in order: a list of (gamma name, [(ops, keys, vals), ...])."""
+    seed: int
+    hash_a: int
+    hash_b: int
+    keys: np.ndarray
+    vals: np.ndarray
+    batch: int
+    checkpoints: list
+    mixed: list
+    mixed_inserts: int
+
+
+def growth_checkpoints(seed: int, total: int, batch: int, checkpoints, per_gamma: int,
+                       length: int, prime: int, gammas=GAMMAS) -> Growth:
+    """Keys for growth to `total` in batches of `batch`, and at each checkpoint `per_gamma`
+    mixed batches of `length` ops for every operation distribution in `gammas`. A mixed batch
+    inserts fresh keys, deletes distinct keys present at its start, searches present keys
+    (uniformly, with repeats) and searches keys never inserted, shuffled. Keys come from
+    `distinct_keys` ranges, so growth keys, fresh keys and absent keys are pairwise disjoint."""
+    assert all(0 < c <= total for c in checkpoints) and list(checkpoints) == sorted(checkpoints)
+    rng = SplitMix64(seed)
+    a, b = hash_params(rng, prime)
+    keys = distinct_keys(seed, 0, total)
+    counts = {g: gamma_counts(length, f) for g, f in gammas.items()}
+    n_fresh = len(checkpoints) * per_gamma * sum(c[0] for c in counts.values())
+    n_absent = max(1, max(c[3] for c in counts.values()))
+    fresh = distinct_keys(seed, total, n_fresh)
+    absent = distinct_keys(seed, total + n_fresh, 4 * n_absent)
+    present = np.empty(0, dtype=np.uint32)
+    grown, fi, mixed = 0, 0, []
+    for cp in checkpoints:
+        present = np.concatenate([present, keys[grown:cp]])
+        grown = cp
+        per_cp = []
+        for g in gammas:
+            n_ins, n_del, n_hit, n_miss = counts[g]
+            bl = []
+            for _ in range(per_gamma):
+                dpos = sample_distinct(rng, n_del, present.size)
+                dels = present[dpos]
+                hits = present[rng.below(n_hit, present.size)] if n_hit else present[:0]
+                miss = absent[rng.below(n_miss, absent.size)] if n_miss else absent[:0]
+                ins = fresh[fi:fi + n_ins]
+                fi += n_ins
+                k = np.concatenate([ins, dels, hits, miss]).astype(np.uint32)
+                o = np.concatenate([np.full(n_ins, OP_INSERT), np.full(n_del, OP_DELETE),
+                                    np.full(n_hit + n_miss, OP_SEARCH)]).astype(np.uint8)
+                perm = rng.permutation(k.size)
+                k, o = k[perm], o[perm]
+                bl.append((o, k, value_of(k)))
+                present = np.concatenate([np.delete(present, dpos), ins])
+            per_cp.append((g, bl))
+        mixed.append(per_cp)
+    return Growth(seed, a, b, keys, value_of(keys), batch, list(checkpoints), mixed, fi)
+
+
 def sample_distinct(rng: SplitMix64, k: int, n: int, ok: np.ndarray | None = None) -> np.ndarray:
     """k distinct indices in [0, n) (optionally only where ok[idx]), in draw order."""
     avail = n if ok is None else int(np.count_nonzero(ok[:n]))
@@ -387,10 +453,18 @@ class ServedRequests:
     mut_keys: np.ndarray = None  # keys some request mutates (each exactly once)
     mut_req: np.ndarray = None   # the request mutating mut_keys[i]
 
-    @property
-    def mutator(self) -> dict:
-        """key -> index of the request that mutates it."""
-        return dict(zip(self.mut_keys.tolist(), self.mut_req.tolist()))
+    def mutator_of(self, keys: np.ndarray) -> np.ndarray:
+        """For each key, the index of the request that mutates it, or -1 if none does."""
+        keys = np.asarray(keys, dtype=np.uint32)
+        out = np.full(keys.shape, -1, dtype=np.int64)
+        if self.mut_keys is None or self.mut_keys.size == 0:
+            return out
+        order = np.argsort(self.mut_keys, kind="stable")
+        sk = self.mut_keys[order]
+        pos = np.minimum(np.searchsorted(sk, keys), sk.size - 1)
+        hit = sk[pos] == keys
+        out[hit] = self.mut_req[order][pos[hit]]
+        return out
 
 
 def served_requests(seed: int, initial: np.ndarray, n_req: int, len_lo: int, len_hi: int,

@@ -130,3 +130,48 @@ def test_distinct_keys_are_distinct_and_disjoint():
     # roughly uniform: the top 4 bits are balanced
     counts = np.bincount(a >> np.uint32(28), minlength=16)
     assert counts.min() > 0.9 * a.size / 16
+
+
+def test_growth_checkpoints_properties():
+    """Growth keys are distinct; every mixed batch inserts fresh keys, deletes distinct keys
+    present at its start, searches present or never-inserted keys, in the paper's proportions."""
+    g = W.growth_checkpoints(seed=5, total=6000, batch=512, checkpoints=[1000, 6000],
+                             per_gamma=3, length=400, prime=4294967291)
+    assert np.unique(g.keys).size == g.keys.size and (g.keys != W.RESERVED_KEY).all()
+    present = set()
+    grown = 0
+    inserted = set(g.keys.tolist())
+    for cp, per_cp in zip(g.checkpoints, g.mixed):
+        present |= set(g.keys[grown:cp].tolist())
+        grown = cp
+        assert [name for name, _ in per_cp] == list(W.GAMMAS)
+        for name, batches in per_cp:
+            n_ins, n_del, n_hit, n_miss = W.gamma_counts(400, W.GAMMAS[name])
+            for ops, keys, vals in batches:
+                assert ops.size == keys.size == vals.size == 400
+                assert (vals == W.value_of(keys)).all()
+                ins, dels = keys[ops == W.OP_INSERT], keys[ops == W.OP_DELETE]
+                srch = keys[ops == W.OP_SEARCH]
+                assert ins.size == n_ins and dels.size == n_del and srch.size == n_hit + n_miss
+                assert not (set(ins.tolist()) & inserted)          # fresh
+                assert np.unique(dels).size == dels.size and set(dels.tolist()) <= present
+                hit = np.array([k in present for k in srch.tolist()], dtype=bool)
+                assert int(hit.sum()) == n_hit                      # the rest never inserted
+                assert not (set(srch[~hit].tolist()) & inserted)
+                inserted |= set(ins.tolist())
+                present = (present - set(dels.tolist())) | set(ins.tolist())
+    assert g.mixed_inserts == sum(W.gamma_counts(400, f)[0] for f in W.GAMMAS.values()) * 3 * 2
+
+
+def test_served_mutator_lookup():
+    rng = W.SplitMix64(9)
+    init = W.unique_keys(rng, 5000)
+    sr = W.served_requests(10, init, 60, 1, 300, zipf_s=1.1, absent_frac=0.1)
+    want = dict(zip(sr.mut_keys.tolist(), sr.mut_req.tolist()))
+    got = sr.mutator_of(sr.keys)
+    assert got.tolist() == [want.get(k, -1) for k in sr.keys.tolist()]
+    assert (sr.mutator_of(np.array([], np.uint32)).size == 0)
+    # every mutating op's key maps to its own request
+    req = np.searchsorted(sr.offsets, np.arange(sr.keys.size), side="right") - 1
+    mut = sr.ops != W.OP_SEARCH
+    assert (got[mut] == req[mut]).all()

@@ -79,3 +79,33 @@ def test_growth_to_2p24_with_mixed_checkpoints(oracle_mod):
             dels = bk[ops == 2]
             present = np.concatenate([present[~np.isin(present, dels)], bk[ops == 1]])
     assert_same_table(t, o)
+
+
+def test_growth_with_all_three_distributions(oracle_mod):
+    """The concurrent benchmark's workload at reduced size: growth in insert batches, and at
+    each checkpoint mixed batches of Gamma0, Gamma1 and Gamma2, every batch checked per key
+    against the oracle and the final table compared in full."""
+    say("case: growth to 2^19 with Gamma0/1/2 batches at 2^17 and 2^19")
+    total, batch, B = 1 << 19, 1 << 14, 24787
+    g = W.growth_checkpoints(61, total, batch, [1 << 17, 1 << 19], 2, 1 << 14,
+                             S.SH_HASH_PRIME)
+    t, o = make(oracle_mod, B, g.hash_a, g.hash_b,
+                S.pool_slabs_bound(total + g.mixed_inserts))
+    kd, vd = S.to_dev(g.keys), S.to_dev(g.vals)
+    grown = 0
+    for cp, per_cp in zip(g.checkpoints, g.mixed):
+        for s0 in range(grown, cp, batch):
+            st = t.insert(kd[s0:s0 + batch], vd[s0:s0 + batch])
+            assert bool((st == 1).all())
+        o.replace(g.keys[grown:cp], g.vals[grown:cp])
+        grown = cp
+        for name, batches in per_cp:
+            say("  %d keys, %s" % (cp, name))
+            for ops, bk, bv in batches:
+                pre_v, pre_f, _ = o.search(bk)
+                gv, gs = t.mixed(S.to_dev(ops), S.to_dev(bk), S.to_dev(bv))
+                ov, ost = o.mixed(ops, bk, bv)
+                post_v, post_f, _ = o.search(bk)
+                LZ.check_single_mutation_batch(ops, bk, S.to_host_u32(gv), gs.cpu().numpy(),
+                                               pre_f, pre_v, post_f, post_v, ost)
+    assert_same_table(t, o)

@@ -90,7 +90,7 @@ def test_same_alone_and_in_the_mix(oracle_mod):
     va, sa = S.to_host_u32(va), sa.cpu().numpy()
     mut = sr.ops != W.OP_SEARCH
     assert (sa[mut] == sb[mut]).all() and (sa[mut] == 1).all()
-    own = np.array([sr.mutator.get(int(k), -1) for k in sr.keys]) == req_of(sr)
+    own = sr.mutator_of(sr.keys) == req_of(sr)
     same = ~mut & ~own   # searches of keys their own request does not mutate
     assert (sa[same] == sb[same]).all() and (va[same] == vb[same]).all()
     pre_f, pre_v, post_f, post_v = states(sr, dict(zip(init.tolist(), vals0.tolist())))
@@ -134,7 +134,7 @@ def test_zipf_requests_linearizable_in_real_time(oracle_mod):
     assert (gs[mut] == 1).all()
     pre_f, pre_v, post_f, post_v = states(sr, dict(zip(init.tolist(), vals0.tolist())))
     q = req_of(sr)
-    r = np.array([sr.mutator.get(int(k), -1) for k in sr.keys])
+    r = sr.mutator_of(sr.keys)
     srch = ~mut
     ok_pre = (gs == pre_f) & ((gs == 0) | (gv == pre_v))
     ok_post = (gs == post_f) & ((gs == 0) | (gv == post_v))
