@@ -65,6 +65,7 @@ def _load():
             "om_utilisation": ([P, D, D], D),
             "om_dump": ([P, P, P, P, U64], U64),
             "om_flush_all": ([P], None),
+            "om_flush_buckets": ([P, U32, U32], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -172,3 +173,9 @@ class Oracle:
 
     def flush_all(self) -> None:
         self._l.om_flush_all(self._t)
+
+    def flush(self, first: int = 0, count: int | None = None) -> None:
+        """FLUSH of buckets [first, first + count) (all from `first` if count is None)."""
+        if count is None:
+            count = max(0, self.B - first)
+        self._l.om_flush_buckets(self._t, int(first), int(count))

@@ -193,11 +193,12 @@ int om_search(const om_table *t, uint32_t k, uint32_t *val, uint32_t *slabs_visi
     return 1;
 }
 
-/* FLUSH of every bucket: drop deleted elements and release slabs no longer needed
-   ("Flush" subsection). Live elements keep their relative order. */
-void om_flush_all(om_table *t)
+/* FLUSH of buckets first .. first + count - 1 (those below B): drop deleted elements and
+   release the slabs no longer needed ("Flush" subsection). Live elements keep their relative
+   order. */
+void om_flush_buckets(om_table *t, uint32_t first, uint32_t count)
 {
-    for (uint32_t i = 0; i < t->B; i++) {
+    for (uint64_t i = first; i < (uint64_t)first + count && i < t->B; i++) {
         om_bucket *bk = &t->bk[i];
         uint32_t before = slabs_for(bk->n, t->M), w = 0;
         for (uint32_t r = 0; r < bk->n; r++)
@@ -206,6 +207,12 @@ void om_flush_all(om_table *t)
         bk->n = w;
         t->pool_used -= before - slabs_for(bk->n, t->M);
     }
+}
+
+/* FLUSH of every bucket. */
+void om_flush_all(om_table *t)
+{
+    om_flush_buckets(t, 0, t->B);
 }
 
 /* ---- batched drivers: apply ops one after another in array order ---- */

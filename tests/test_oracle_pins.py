@@ -79,6 +79,19 @@ class SlabListModel:
                     return 1, spot[1], j + 1
         return 0, EMPTY, len(slabs)
 
+    def flush(self, b):
+        """Walk bucket b's slabs head to tail, keep the live spots in the order met, and lay them
+        out again from the head, one slab per M spots (at least one slab); the slabs no longer
+        needed go back to the pool."""
+        kept = [spot for slab in self.lists[b] for spot in slab if spot is not None and spot[2]]
+        slabs = [[None] * self.M]
+        for spot in kept:
+            if slabs[-1][-1] is not None:
+                slabs.append([None] * self.M)
+            slabs[-1][slabs[-1].index(None)] = spot
+        self.pool_used -= len(self.lists[b]) - len(slabs)
+        self.lists[b] = slabs
+
     def stats(self):
         live = [sum(1 for s in l for p in s if p is not None and p[2]) for l in self.lists]
         tomb = [sum(1 for s in l for p in s if p is not None and not p[2]) for l in self.lists]
@@ -130,6 +143,45 @@ def test_oracle_matches_slab_list_model(oracle_mod, B, M):
         probe = np.arange(domain, dtype=np.uint32)
         _, _, visits = o.search(probe)
         assert [model.search(int(k))[2] for k in probe] == visits.tolist()
+
+
+@pytest.mark.parametrize("B,M", [(1, 2), (3, 1), (3, 3), (5, 2)])
+def test_oracle_flush_matches_slab_list_model(oracle_mod, B, M):
+    """Segments of random ops with a flush of a random bucket range after each; the bucket
+    stats, the pool count, the live set and the slabs a search of each key visits (which pins
+    the order the live elements end up in) must match the literal model after every flush."""
+    rng = W.SplitMix64(2000 + 10 * B + M)
+    for trial in range(25):
+        a, b = W.hash_params(rng, oracle_mod.PRIME)
+        o = oracle_mod.Oracle(B, M, a, b)
+        model = SlabListModel(lambda k: int(o.bucket_of([k])[0]), B, M)
+        domain = int(rng.below(1, 20)[0]) + 4
+        for seg in range(6):
+            n_ops = 40
+            ops = rng.below(n_ops, 3).astype(np.uint8)
+            keys = rng.below(n_ops, domain).astype(np.uint32)
+            vals = (rng.next(n_ops) >> np.uint64(32)).astype(np.uint32)
+            o.mixed(ops, keys, vals)
+            for i in range(n_ops):
+                k, v = int(keys[i]), int(vals[i])
+                (model.search, lambda k, v=v: model.replace(k, v), model.delete)[ops[i]](k)
+            first = int(rng.below(1, B)[0])
+            count = int(rng.below(1, B + 1)[0])
+            o.flush(first, count)
+            for bb in range(first, min(B, first + count)):
+                model.flush(bb)
+            live, tomb, slabs = o.bucket_stats()
+            ml, mt, ms = model.stats()
+            assert list(live) == ml and list(tomb) == mt and list(slabs) == ms, (trial, seg)
+            assert o.pool_used == model.pool_used == sum(s - 1 for s in ms)
+            db, dk, dv = o.dump()
+            assert sorted(zip(db.tolist(), dk.tolist(), dv.tolist())) == model.dump()
+            probe = np.arange(domain, dtype=np.uint32)
+            _, _, visits = o.search(probe)
+            assert [model.search(int(k))[2] for k in probe] == visits.tolist()
+    # flushing every bucket leaves no deleted spots
+    o.flush_all()
+    assert o.bucket_stats()[1].sum() == 0
 
 
 # ---------------------------------------------------------------------------------------------
