@@ -378,6 +378,44 @@ def run_served(seed: int = 41, n_keys: int = 1 << 26, n_req: int = 10000,
     }
 
 
+def measure_flush(table, keys, vals, st, stream, reps: int = 5) -> dict:
+    """FLUSH of every bucket ("Flush" subsection) of the benchmark table after half of its 2^22
+    keys have been deleted: median of `reps` runs, each on a freshly built and half-deleted
+    table. Algorithmic bytes: every slab read once, every kept slab written, every freed slab
+    reset (256 bytes each)."""
+    import torch
+    from paper_1710_11246_amd import slabhash as S
+    h = table.handle
+    half = keys[: keys.numel() // 2]
+    dst = torch.empty(half.numel(), dtype=torch.uint8, device=keys.device)
+    ts = []
+    for _ in range(reps):
+        S.sh_reset(h, stream)
+        S.sh_build(h, keys, vals, st, stream)
+        S.sh_delete(h, half, dst, stream)
+        before = table.stats()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        S.sh_flush(h, 0, table.num_buckets, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+        after = table.stats()
+    assert after["tombstones"] == 0 and after["violations"] == 0
+    freed = before["pool_allocated"] - after["pool_allocated"]
+    ms = float(np.median(ts))
+    nbytes = 256.0 * (before["slabs_total"] + after["slabs_total"] + freed)
+    return {"workload": "2^22 keys at B=%d, half deleted, flush of every bucket"
+                        % table.num_buckets,
+            "avg_ms": round(ms, 4), "slabs_before": before["slabs_total"],
+            "slabs_after": after["slabs_total"], "slabs_freed": freed,
+            "tombstones_before": before["tombstones"],
+            "Mbuckets_per_s": round(table.num_buckets / (ms * 1e-3) / 1e6, 1),
+            "algorithmic_GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
     """Ceilings of the operation kernels' memory access patterns, from libslabhash_roofs.so, over
     a buffer of nbytes (the benchmark table's size): n_ops random 256-byte slab reads (the
@@ -550,6 +588,9 @@ def main():
             "traffic": TRAFFIC_BYTES[dom] if traffic_ok else None, "kernel": dom,
             "bytes_per_launch": int(bytes_l[dom])}
 
+    log("flush")
+    flush = measure_flush(table, keys, vals, st_build, stream)
+
     log("access-pattern ceilings")
     patterns = measure_patterns(int(table.storage.numel()), N_KEYS)
     # each kernel against the ceiling of its own access pattern, measured above
@@ -652,6 +693,7 @@ def main():
         "build_counters": build_counters,
         "roofline": roof,
         "access_patterns": patterns,
+        "flush": flush,
         "cpu_baseline": cpu,
     }
     if sweep is not None:

@@ -114,6 +114,17 @@ sh_status_t sh_create(const sh_params_t *p, void *d_storage, size_t bytes, void 
 /* Re-initialise the table in place (same as the initialisation done by sh_create). */
 sh_status_t sh_reset(sh_table_t *t, void *stream);
 
+/* FLUSH ("Flush" subsection) of buckets first_bucket .. first_bucket + num_buckets - 1. In each
+   bucket the live elements move, in list order, to the front of its slab list; deleted elements
+   are dropped; the list is cut to max(1, ceil(live / 31)) slabs, and the slabs cut off are reset
+   to empty and returned to the pool. Later operations give the same results as without the
+   flush; only the layout, the deleted count and the slab count change. Like sh_reset it must not
+   overlap any other call on the table. (A server started on the table counts pool use from the
+   allocations it sees, so slabs a flush frees become available to its admission only after it
+   is restarted.) Requires first_bucket <= B and num_buckets <= B - first_bucket, else
+   SH_EINVAL; num_buckets == 0 is a no-op. Asynchronous on `stream`. */
+sh_status_t sh_flush(sh_table_t *t, uint32_t first_bucket, uint32_t num_buckets, void *stream);
+
 /* Free the host handle only; the device storage stays the caller's. Handles that belong to a
    multi-table object (sh_multi_table) give SH_EINVAL. */
 sh_status_t sh_destroy(sh_table_t *t);

@@ -3,7 +3,7 @@
 // Paper: Ashkiani, Farach-Colton, Owens, "A Dynamic Hash Table for the GPU".
 //
 // Memory layout of one table (one caller-owned device allocation, 256-byte aligned):
-//   [header 256 B][B base slabs][P pool slabs][P/2048 bitmap rows of 256 B]
+//   [header 4 KB][B base slabs][P pool slabs][P/2048 bitmap rows of 256 B]
 // A slab is 256 B = 32 eight-byte words. Words 0..30 are key/value slots (key in the low half,
 // value in the high half); word 31 holds an auxiliary half (always 0xFFFFFFFF) and the index
 // of the next pool slab (0xFFFFFFFF = none) in its high half. Slot encodings:
@@ -676,6 +676,95 @@ __global__ __launch_bounds__(kBlock) void walk_kernel(View T, uint32_t *__restri
     }
 }
 
+// FLUSH ("Flush" subsection): one wavefront per bucket of [first, first + count), grid-stride.
+// The wavefront walks the bucket's list head to tail and moves its live pairs, in the order it
+// meets them, to the front of the list. The slab that receives the last live pair (the base
+// slab if there is none) becomes the tail: its remaining slots are emptied and its next index
+// cleared. The slabs after it are reset to all ones, so a later allocation finds them empty, and
+// returned to the allocator. The write position never passes the end of the slab being read
+// (a slab holds at most 31 live pairs), so every slab is read before anything is written into
+// it; the next index of a slab is never written before the walk has passed it. This is a kernel
+// of its own: no operation touches the table while it runs. A next index outside the pool (a
+// well-formed table has none; the structure walk of sh_stats reports one) leaves the rest of
+// that bucket as it is.
+__global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, uint32_t count)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t slot = lane & 31;
+    const uint32_t below = (1u << slot) - 1u;
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    for (uint32_t i = wave; i < count; i += nwaves) {
+        const uint32_t bkt = first + i;
+        uint32_t ru = bkt;         // unified index of the slab being read
+        uint32_t wu = bkt, ws = 0; // write position: slot ws of slab wu (31 = wu is full)
+        uint32_t seen = 0, nxt = kEmpty;
+        uint64_t w = 0;
+        bool ok = true;
+        for (;;) {
+            w = T.base[(size_t)ru * 32 + slot];
+            nxt = rl((uint32_t)(w >> 32), 31);
+            const bool live = slot < 31 && (uint32_t)w != kEmpty;
+            const uint32_t lm = (uint32_t)ballot(live); // lanes 0..31; 32..63 mirror them
+            const uint32_t cnt = (uint32_t)__popc(lm);
+            if (cnt) {
+                // pairs past slot 30 of wu go to the slab after it, which the walk has passed
+                uint32_t spill = 0;
+                if (ws + cnt > 31) {
+                    spill = (uint32_t)(T.base[(size_t)wu * 32 + 31] >> 32);
+                    if (spill >= T.pool_slabs) {
+                        ok = false;
+                        break;
+                    }
+                }
+                const uint32_t pos = ws + (uint32_t)__popc(lm & below);
+                const uint32_t du = (pos < 31) ? wu : T.B + spill;
+                const uint32_t ds = (pos < 31) ? pos : pos - 31;
+                if (lane < 32 && live && (du != ru || ds != slot)) // pairs already in place stay
+                    T.base[(size_t)du * 32 + ds] = w;
+                if (ws + cnt > 31) {
+                    wu = T.B + spill;
+                    ws = ws + cnt - 31;
+                } else {
+                    ws += cnt;
+                }
+            }
+            if (nxt == kEmpty)
+                break;
+            if (nxt >= T.pool_slabs || ++seen > T.pool_slabs) {
+                ok = false;
+                break;
+            }
+            ru = T.B + nxt;
+        }
+        if (!ok)
+            continue;
+        // the tail: its old next index (already in hand if the tail is the last slab read),
+        // then its slots after the write position are emptied and its next index cleared (word
+        // 31 becomes all ones: auxiliary half and "no next"); words already so are not written
+        uint32_t rest = nxt;
+        if (wu != ru)
+            rest = rl((uint32_t)(T.base[(size_t)wu * 32 + slot] >> 32), 31);
+        // the last slab read still holds its own words in w; an earlier tail is rewritten whole
+        const bool keep = wu == ru && w == kEmptyPair;
+        if (lane < 32 && slot >= ws && !keep)
+            T.base[(size_t)wu * 32 + slot] = kEmptyPair;
+        // the slabs that followed the tail go back to the pool, emptied
+        uint32_t f = rest;
+        seen = 0;
+        while (f != kEmpty) {
+            if (f >= T.pool_slabs || ++seen > T.pool_slabs)
+                break;
+            const uint32_t nf = rl((uint32_t)(T.pool[(size_t)f * 32 + slot] >> 32), 31);
+            if (lane < 32)
+                T.pool[(size_t)f * 32 + slot] = kEmptyPair;
+            if (lane == 0)
+                slab_free(T, f);
+            f = nf;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void popcount_kernel(View T)
 {
     const size_t nw = (size_t)T.nblk * 64;
@@ -1004,6 +1093,23 @@ sh_status_t sh_reset(sh_table_t *t, void *stream)
     if (!t)
         return SH_EINVAL;
     return launch_init(t, stream);
+}
+
+sh_status_t sh_flush(sh_table_t *t, uint32_t first_bucket, uint32_t num_buckets, void *stream)
+{
+    if (!t || first_bucket > t->p.num_buckets || num_buckets > t->p.num_buckets - first_bucket)
+        return SH_EINVAL;
+    if (num_buckets == 0)
+        return SH_OK;
+    // a light kernel bound by the latency of walking each list: twice the operation kernels'
+    // wavefronts per compute unit
+    uint64_t waves = (uint64_t)t->num_cu * 2 * kDefaultWavesPerCU;
+    if (waves > num_buckets)
+        waves = num_buckets;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(flush_kernel, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
+                       first_bucket, num_buckets);
+    return check_launch();
 }
 
 sh_status_t sh_destroy(sh_table_t *t)

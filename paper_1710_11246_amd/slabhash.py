@@ -78,6 +78,7 @@ _SIGS = {
     "sh_storage_bytes": ([_P], _SZ),
     "sh_create": ([_P, _P, _SZ, _P, _P], ctypes.c_int),
     "sh_reset": ([_P, _P], ctypes.c_int),
+    "sh_flush": ([_P, _U32, _U32, _P], ctypes.c_int),
     "sh_destroy": ([_P], ctypes.c_int),
     "sh_set_launch": ([_P, _P], ctypes.c_int),
     "sh_build": ([_P, _P, _P, _U64, _P, _P], ctypes.c_int),
@@ -186,6 +187,10 @@ def sh_create(params: ShParams, storage: torch.Tensor, stream=None) -> ctypes.c_
 
 def sh_reset(t, stream=None) -> None:
     _check("sh_reset", lib().sh_reset(t, _stream(stream)))
+
+
+def sh_flush(t, first_bucket: int, num_buckets: int, stream=None) -> None:
+    _check("sh_flush", lib().sh_flush(t, int(first_bucket), int(num_buckets), _stream(stream)))
 
 
 def sh_destroy(t) -> None:
@@ -469,6 +474,12 @@ class SlabHash:
 
     def set_launch(self, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0):
         sh_set_launch(self.handle, waves_per_cu, ops_per_wave, flags)
+
+    def flush(self, first: int = 0, count: int | None = None, stream=None):
+        """FLUSH of buckets [first, first + count) (every bucket from `first` by default)."""
+        if count is None:
+            count = self.num_buckets - first
+        sh_flush(self.handle, first, count, stream)
 
     def insert(self, keys, vals, stream=None, status=True):
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
