@@ -416,6 +416,42 @@ def measure_flush(table, keys, vals, st, stream, reps: int = 5) -> dict:
             "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def measure_alloc(n: int = 1 << 20, reps: int = 5) -> dict:
+    """SlabAlloc on its own, as the paper measures it ("Dynamic memory allocation": a million
+    slab allocations, one per thread): n allocations from a pool with 4 spare blocks, then the
+    same n from a pool of exactly n slabs (the last ones must hunt for the remaining free bits),
+    then freeing all n. Median of `reps` runs each, on a freshly initialised pool."""
+    import torch
+    from paper_1710_11246_amd import slabhash as S
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    res = {"workload": "%d slab allocations (256-byte slabs), one per lane" % n}
+    for name, pool in (("alloc", n + 4 * 2048), ("alloc_full_pool", n)):
+        t = S.SlabHash(1, pool, 3, 5)
+        ts, tf = [], []
+        for _ in range(reps):
+            t.reset()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            S.sh_alloc_slabs(t.handle, n, out)
+            e[1].record()
+            S.sh_free_slabs(t.handle, out)
+            e[2].record()
+            torch.cuda.synchronize()
+            ts.append(e[0].elapsed_time(e[1]))
+            tf.append(e[1].elapsed_time(e[2]))
+        got = S.to_host_u32(out)
+        assert np.unique(got).size == n and (got < pool).all()
+        ms = float(np.median(ts))
+        res[name + "_ms"] = round(ms, 4)
+        res[name + "_Mslabs_per_s"] = round(n / (ms * 1e-3) / 1e6, 1)
+        if name == "alloc":
+            msf = float(np.median(tf))
+            res["free_ms"] = round(msf, 4)
+            res["free_Mslabs_per_s"] = round(n / (msf * 1e-3) / 1e6, 1)
+        del t
+    return res
+
+
 def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
     """Ceilings of the operation kernels' memory access patterns, from libslabhash_roofs.so, over
     a buffer of nbytes (the benchmark table's size): n_ops random 256-byte slab reads (the
@@ -591,6 +627,9 @@ def main():
     log("flush")
     flush = measure_flush(table, keys, vals, st_build, stream)
 
+    log("allocator")
+    allocator = measure_alloc()
+
     log("access-pattern ceilings")
     patterns = measure_patterns(int(table.storage.numel()), N_KEYS)
     # each kernel against the ceiling of its own access pattern, measured above
@@ -694,6 +733,7 @@ def main():
         "roofline": roof,
         "access_patterns": patterns,
         "flush": flush,
+        "allocator": allocator,
         "cpu_baseline": cpu,
     }
     if sweep is not None:

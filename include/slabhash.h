@@ -125,6 +125,23 @@ sh_status_t sh_reset(sh_table_t *t, void *stream);
    SH_EINVAL; num_buckets == 0 is a no-op. Asynchronous on `stream`. */
 sh_status_t sh_flush(sh_table_t *t, uint32_t first_bucket, uint32_t num_buckets, void *stream);
 
+/* SlabAlloc on its own ("Dynamic memory allocation"), for measuring and testing the allocator
+   the way the paper does (one million slab allocations, one per thread). Request i of n is
+   served by lane i % 64 of wavefront i / 64; the wavefront serves its lanes one at a time from
+   its resident block, as when a list needs a new slab. d_out[i] (device, n entries) receives
+   the pool index of a free slab, now marked allocated, or 0xFFFFFFFF once the pool is exhausted
+   (SH_ERR_POOL_EXHAUSTED is then set in the error word). The slabs belong to no list: use a
+   table set aside for this, or return them with sh_free_slabs before the table serves
+   operations again (sh_stats counts them in pool_allocated). n < 2^32, else SH_EINVAL; n == 0 is
+   a no-op. Asynchronous; must not overlap other calls on the table. */
+sh_status_t sh_alloc_slabs(sh_table_t *t, uint64_t n, uint32_t *d_out, void *stream);
+
+/* Return slabs to the pool: the bit of every entry of d_idx (device, n entries) below the pool
+   size is cleared in its block's bitmap; other entries are skipped. The slabs must belong to no
+   list and still be empty (all ones), as allocation hands them out: allocations do not clear
+   slabs. n < 2^32, else SH_EINVAL. Asynchronous; must not overlap other calls on the table. */
+sh_status_t sh_free_slabs(sh_table_t *t, const uint32_t *d_idx, uint64_t n, void *stream);
+
 /* Free the host handle only; the device storage stays the caller's. Handles that belong to a
    multi-table object (sh_multi_table) give SH_EINVAL. */
 sh_status_t sh_destroy(sh_table_t *t);

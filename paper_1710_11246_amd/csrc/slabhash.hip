@@ -155,8 +155,9 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
 // blocks of 2048 slabs; a block's occupancy is one 256-byte bitmap row, which a wavefront holds
 // in registers as one 32-bit word per lane (lane l covers slabs 32l .. 32l+31 of the block).
 // The wavefront's "resident" block serves its allocations: lanes with a free bit vote, the
-// lowest such lane claims its lowest free bit with an atomic OR on the row in memory and, if the
-// bit was still free, broadcasts the slab index. A lost race refreshes that lane's word. When
+// first such lane in the wavefront's own priority order (lane order rotated by a per-wavefront
+// offset) claims its lowest free bit with an atomic OR on the row in memory and, if the bit was
+// still free, broadcasts the slab index. A lost race refreshes that lane's word. When
 // the resident block is full the wavefront moves to the next block, reading its row with one
 // coalesced load; after a full cycle of blocks without success the pool counts as exhausted.
 
@@ -166,6 +167,7 @@ struct Alloc {
     uint32_t moves; // block moves since the last successful allocation
     uint32_t total_moves;
     uint32_t start; // first block tried
+    uint32_t rot;   // this wavefront's rotation of the lane priority order
     bool full;      // this wavefront found the pool exhausted
 };
 
@@ -181,7 +183,11 @@ __device__ uint32_t wave_alloc(const View &T, Alloc &s, uint32_t lane)
     for (;;) {
         const uint64_t free_lanes = ballot(s.word != kEmpty);
         if (free_lanes) {
-            const uint32_t l = ffs0(free_lanes);
+            // the first lane with a free slab in this wavefront's priority order: lanes
+            // rot, rot + 1, ..., 63, 0, ... (wavefronts sharing a block start at different
+            // bitmap words instead of all claiming the same bit)
+            const uint64_t r = (free_lanes >> s.rot) | (free_lanes << ((64u - s.rot) & 63u));
+            const uint32_t l = (ffs0(r) + s.rot) & 63u;
             uint32_t got = kEmpty;
             if (lane == l) {
                 const uint32_t bit = (uint32_t)__builtin_ctz(~s.word);
@@ -476,6 +482,7 @@ __device__ __forceinline__ void alloc_init(Alloc &al, uint32_t wave, uint32_t se
     al.total_moves = 0;
     al.full = false;
     al.start = mix32(wave * 0x9E3779B9u + seq);
+    al.rot = mix32(al.start) & 63u;
 }
 
 template <int K>
@@ -762,6 +769,47 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
                 slab_free(T, f);
             f = nf;
         }
+    }
+}
+
+// SlabAlloc on its own ("Dynamic memory allocation"): request i of n is served by lane i % 64 of
+// wavefront i / 64. The wavefront serves its lanes' requests one at a time from its resident
+// block, as the replace step does when a list needs a new slab. out[i] receives the pool index,
+// or kEmpty once the pool is exhausted.
+__global__ __launch_bounds__(kBlock) void alloc_kernel(View T, uint64_t n,
+                                                       uint32_t *__restrict__ out, uint32_t seq)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint64_t i0 = wave * 64;
+    if (i0 >= n)
+        return; // the whole wavefront
+    const uint32_t cnt = (n - i0 < 64) ? (uint32_t)(n - i0) : 64u;
+    Alloc al;
+    alloc_init(al, (uint32_t)wave, seq);
+    uint32_t mine = kEmpty;
+    bool failed = false;
+    for (uint32_t j = 0; j < cnt; ++j) {
+        const uint32_t idx = wave_alloc(T, al, lane);
+        if (lane == j)
+            mine = idx;
+        failed = failed || idx == kEmpty;
+    }
+    if (failed)
+        raise_error(T, SH_ERR_POOL_EXHAUSTED, lane, 0);
+    if (lane < cnt)
+        out[i0 + lane] = mine;
+}
+
+// Deallocation: unset each slab's bit in its block's bitmap; entries outside the pool are skipped.
+__global__ __launch_bounds__(kBlock) void free_kernel(View T, const uint32_t *__restrict__ idx,
+                                                      uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t f = idx[i];
+        if (f < T.pool_slabs)
+            slab_free(T, f);
     }
 }
 
@@ -1109,6 +1157,33 @@ sh_status_t sh_flush(sh_table_t *t, uint32_t first_bucket, uint32_t num_buckets,
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(flush_kernel, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
                        first_bucket, num_buckets);
+    return check_launch();
+}
+
+sh_status_t sh_alloc_slabs(sh_table_t *t, uint64_t n, uint32_t *d_out, void *stream)
+{
+    if (!t || (n && !d_out) || n >= (1ull << 32))
+        return SH_EINVAL;
+    if (n == 0)
+        return SH_OK;
+    const uint64_t blocks = (n + kBlock - 1) / kBlock; // one request per lane
+    hipLaunchKernelGGL(alloc_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, S(stream), t->v, n,
+                       d_out, t->seq++);
+    return check_launch();
+}
+
+sh_status_t sh_free_slabs(sh_table_t *t, const uint32_t *d_idx, uint64_t n, void *stream)
+{
+    if (!t || (n && !d_idx) || n >= (1ull << 32))
+        return SH_EINVAL;
+    if (n == 0)
+        return SH_OK;
+    uint64_t blocks = (n + kBlock - 1) / kBlock;
+    const uint64_t cap = (uint64_t)t->num_cu * 8;
+    if (blocks > cap)
+        blocks = cap;
+    hipLaunchKernelGGL(free_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, S(stream), t->v,
+                       d_idx, n);
     return check_launch();
 }
 

@@ -79,6 +79,8 @@ _SIGS = {
     "sh_create": ([_P, _P, _SZ, _P, _P], ctypes.c_int),
     "sh_reset": ([_P, _P], ctypes.c_int),
     "sh_flush": ([_P, _U32, _U32, _P], ctypes.c_int),
+    "sh_alloc_slabs": ([_P, _U64, _P, _P], ctypes.c_int),
+    "sh_free_slabs": ([_P, _P, _U64, _P], ctypes.c_int),
     "sh_destroy": ([_P], ctypes.c_int),
     "sh_set_launch": ([_P, _P], ctypes.c_int),
     "sh_build": ([_P, _P, _P, _U64, _P, _P], ctypes.c_int),
@@ -191,6 +193,17 @@ def sh_reset(t, stream=None) -> None:
 
 def sh_flush(t, first_bucket: int, num_buckets: int, stream=None) -> None:
     _check("sh_flush", lib().sh_flush(t, int(first_bucket), int(num_buckets), _stream(stream)))
+
+
+def sh_alloc_slabs(t, n: int, out: torch.Tensor, stream=None) -> None:
+    o = _dev(out, "out", _U32_TYPES, n)
+    _check("sh_alloc_slabs", lib().sh_alloc_slabs(t, int(n), o, _stream(stream)))
+
+
+def sh_free_slabs(t, idx: torch.Tensor, stream=None) -> None:
+    n = idx.numel()
+    p = _dev(idx, "idx", _U32_TYPES, n)
+    _check("sh_free_slabs", lib().sh_free_slabs(t, p, int(n), _stream(stream)))
 
 
 def sh_destroy(t) -> None:

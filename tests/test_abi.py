@@ -58,6 +58,8 @@ def test_argument_errors_before_any_device_call(lib):
     assert lib.sh_dump(None, None, None, None, 0, None, None, None, None) == S.SH_EINVAL
     assert lib.sh_reset(None, None) == S.SH_EINVAL
     assert lib.sh_flush(None, 0, 1, None) == S.SH_EINVAL
+    assert lib.sh_alloc_slabs(None, 10, 256, None) == S.SH_EINVAL
+    assert lib.sh_free_slabs(None, 256, 10, None) == S.SH_EINVAL
     assert lib.sh_destroy(None) == S.SH_EINVAL
     assert lib.sh_set_launch(None, None) == S.SH_EINVAL
 

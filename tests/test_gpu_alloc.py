@@ -1,0 +1,93 @@
+"""GPU checks of SlabAlloc on its own ("Dynamic memory allocation"): every request gets a distinct
+slab of the pool until the pool is exhausted, the bitmaps count exactly the slabs handed out,
+freed slabs are handed out again, and a table whose pool has been through allocation and
+release still matches the oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1710_11246_amd import slabhash as S
+from paper_1710_11246_amd import workload as W
+
+from test_gpu_parity import assert_same_table, make
+
+pytestmark = pytest.mark.gpu
+EMPTY = 0xFFFFFFFF
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    S.lib()
+
+
+def alloc(t, n):
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    S.sh_alloc_slabs(t.handle, n, out)
+    return S.to_host_u32(out)
+
+
+def test_alloc_free_realloc():
+    say("case: alloc / free / realloc")
+    t = S.SlabHash(1, 64 * 2048, 3, 5)
+    a = alloc(t, 100003)
+    assert (a < t.params.pool_slabs).all() and np.unique(a).size == a.size
+    st = t.stats()
+    assert st["pool_allocated"] == a.size and st["error_word"] == 0
+    rng = W.SplitMix64(5)
+    gone = a[rng.permutation(a.size)[:40000]]
+    S.sh_free_slabs(t.handle, S.to_dev(gone))
+    assert t.stats()["pool_allocated"] == a.size - gone.size
+    b = alloc(t, 60000)
+    held = np.setdiff1d(a, gone)
+    assert (b < t.params.pool_slabs).all() and np.unique(b).size == b.size
+    assert np.intersect1d(b, held).size == 0
+    assert t.stats()["pool_allocated"] == held.size + b.size
+    # entries outside the pool are skipped when freeing
+    S.sh_free_slabs(t.handle, S.to_dev(np.array([EMPTY, t.params.pool_slabs], np.uint32)))
+    assert t.stats()["pool_allocated"] == held.size + b.size
+
+
+def test_alloc_exhaustion():
+    say("case: alloc past the pool")
+    t = S.SlabHash(1, 8 * 2048, 7, 11)
+    a = alloc(t, 8 * 2048 + 777)
+    ok = a != EMPTY
+    assert int(ok.sum()) == 8 * 2048 and np.unique(a[ok]).size == 8 * 2048
+    st = t.stats()
+    assert st["pool_allocated"] == 8 * 2048 and (st["error_word"] & S.SH_ERR_POOL_EXHAUSTED)
+
+
+def test_one_million_allocations():
+    """The paper's allocator test: a million allocations, one per thread."""
+    say("case: 2^20 allocations")
+    n = 1 << 20
+    t = S.SlabHash(1, n + 4 * 2048, 13, 17)
+    a = alloc(t, n)
+    assert (a != EMPTY).all() and np.unique(a).size == n
+    assert t.stats()["pool_allocated"] == n
+    S.sh_free_slabs(t.handle, S.to_dev(a))
+    assert t.stats()["pool_allocated"] == 0
+
+
+def test_table_after_alloc_and_release(oracle_mod):
+    """Slabs taken and given back leave the pool fit for lists: a contended build afterwards
+    matches the oracle."""
+    say("case: table after alloc and release")
+    rng = W.SplitMix64(6)
+    a_, b_ = W.hash_params(rng, S.SH_HASH_PRIME)
+    t, o = make(oracle_mod, 5, a_, b_, 4 * 2048)
+    got = alloc(t, 7000)
+    S.sh_free_slabs(t.handle, S.to_dev(got))
+    keys = W.unique_keys(rng, 20000)
+    vals = W.value_of(keys)
+    assert bool((t.insert(S.to_dev(keys), S.to_dev(vals)) == 1).all())
+    o.replace(keys, vals)
+    assert_same_table(t, o)
