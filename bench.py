@@ -41,9 +41,9 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
 # Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
 # a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
-TRAFFIC_SRC_SHA = "07c89a174112b878"
-TRAFFIC_BYTES = {"build": 1464379874, "search_hit": 1038327028, "search_miss": 1038327028,
-                 "mixed": 19445370, "reset": 94466969}
+TRAFFIC_SRC_SHA = "dca3906ad24f998f"
+TRAFFIC_BYTES = {"build": 1464806017, "search_hit": 1038373685, "search_miss": 1038373685,
+                 "mixed": 19442243, "reset": 94476927}
 
 
 def source_sha() -> str:
@@ -378,6 +378,94 @@ def run_served(seed: int = 41, n_keys: int = 1 << 26, n_req: int = 10000,
     }
 
 
+def sweep_sizes(log2_sizes=(16, 18, 20, 22, 24, 26), util: float = 0.6, reps: int = 5) -> dict:
+    """Bulk build, all-hit search and all-miss search against table size ("Bulk benchmarks"): n
+    distinct uniform keys for each n = 2^k, buckets from the Binomial model for the target
+    utilisation, median of `reps` runs (each build on a reset table)."""
+    import torch
+    from paper_1710_11246_amd import autotune as A
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    out = {}
+    for k in log2_sizes:
+        n = 1 << k
+        keys = W.distinct_keys(100 + k, 0, n)
+        miss = W.distinct_keys(100 + k, n, n)
+        perm = W.SplitMix64(200 + k).permutation(n)
+        rng = W.SplitMix64(300 + k)
+        a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+        B = A.buckets_for_utilisation(n, util)
+        t = S.SlabHash(B, A.pool_slabs_for(n, B), a, b)
+        kd, vd = S.to_dev(keys), S.to_dev(W.value_of(keys))
+        qh, qm = S.to_dev(keys[perm]), S.to_dev(miss)
+        st = torch.empty(n, dtype=torch.uint8, device="cuda")
+        vo = torch.empty(n, dtype=torch.int32, device="cuda")
+        fo = torch.empty(n, dtype=torch.uint8, device="cuda")
+        res = {"build": [], "search_hit": [], "search_miss": []}
+        for _ in range(reps + 1):
+            t.reset()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record()
+            S.sh_build(t.handle, kd, vd, st)
+            e[1].record()
+            S.sh_search(t.handle, qh, vo, fo)
+            e[2].record()
+            S.sh_search(t.handle, qm, vo, fo)
+            e[3].record()
+            torch.cuda.synchronize()
+            for i, nm in enumerate(("build", "search_hit", "search_miss")):
+                res[nm].append(e[i].elapsed_time(e[i + 1]))
+        assert bool((st == 1).all())
+        su = t.stats()
+        out["2^%d" % k] = {
+            "num_buckets": B,
+            "utilisation": round(8.0 * su["live"] / (256.0 * su["slabs_total"]), 4),
+            **{nm + "_Mops": round(n / (float(np.median(v[1:])) * 1e-3) / 1e6, 1)
+               for nm, v in res.items()}}
+        log("  size 2^%d: %s" % (k, out["2^%d" % k]))
+        del t, kd, vd, qh, qm, st, vo, fo
+        torch.cuda.empty_cache()
+    return out
+
+
+def sweep_batches(log2_batches=(15, 16, 17), total: int = 1 << 24, B: int = 793240) -> dict:
+    """Incremental insertion ("Incremental insertion"): 2^24 distinct keys inserted in batches of
+    each size into a table whose final utilisation is about 0.65; the rate over all batches and
+    over the last eighth of them."""
+    import torch
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    keys = W.distinct_keys(71, 0, total)
+    kd, vd = S.to_dev(keys), S.to_dev(W.value_of(keys))
+    rng = W.SplitMix64(72)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    t = S.SlabHash(B, S.pool_slabs_bound(total), a, b)
+    out = {}
+    for k in log2_batches:
+        g = 1 << k
+        t.reset()
+        st = torch.empty(g, dtype=torch.uint8, device="cuda")
+        evs = []
+        for s0 in range(0, total, g):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            S.sh_insert(t.handle, kd[s0:s0 + g], vd[s0:s0 + g], st)
+            e1.record()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = [x.elapsed_time(y) for x, y in evs]
+        tail = ms[-max(1, len(ms) // 8):]
+        su = t.stats()
+        out["2^%d" % k] = {"batches": len(ms),
+                           "Mops_overall": round(total / (sum(ms) * 1e-3) / 1e6, 1),
+                           "Mops_last_eighth": round(g * len(tail) / (sum(tail) * 1e-3) / 1e6, 1),
+                           "final_utilisation": round(
+                               8.0 * su["live"] / (256.0 * su["slabs_total"]), 4)}
+        log("  batch 2^%d: %s" % (k, out["2^%d" % k]))
+    return out
+
+
 def measure_flush(table, keys, vals, st, stream, reps: int = 5) -> dict:
     """FLUSH of every bucket ("Flush" subsection) of the benchmark table after half of its 2^22
     keys have been deleted: median of `reps` runs, each on a freshly built and half-deleted
@@ -497,6 +585,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="also time build/search at every utilisation target")
+    ap.add_argument("--sweep-sizes", action="store_true",
+                    help="also time build/search for table sizes 2^16 .. 2^26 at utilisation 0.6")
+    ap.add_argument("--sweep-batches", action="store_true",
+                    help="also time incremental insertion to 2^24 keys in batches of 2^15..2^17")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form section")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form section")
     ap.add_argument("--no-concurrent", action="store_true",
@@ -682,6 +774,15 @@ def main():
                                 for nm, v in res.items()}}
             del tu
 
+    sizes = None
+    if args.sweep_sizes:
+        log("size sweep")
+        sizes = sweep_sizes()
+    batch_sweep = None
+    if args.sweep_batches:
+        log("batch-size sweep")
+        batch_sweep = sweep_batches()
+
     batched = None
     if not args.no_batched:
         del table
@@ -738,6 +839,10 @@ def main():
     }
     if sweep is not None:
         out["sweep"] = sweep
+    if sizes is not None:
+        out["sweep_sizes"] = sizes
+    if batch_sweep is not None:
+        out["sweep_batches"] = batch_sweep
     if batched is not None:
         out["batched"] = batched
     if concurrent is not None:
