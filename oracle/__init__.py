@@ -66,6 +66,9 @@ def _load():
             "om_dump": ([P, P, P, P, U64], U64),
             "om_flush_all": ([P], None),
             "om_flush_buckets": ([P, U32, U32], None),
+            "om_set_duplicates": ([P, U32], None),
+            "om_delete_all_batch": ([P, P, U64, P], None),
+            "om_search_all_batch": ([P, P, U64, P, P, P], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -87,7 +90,7 @@ class Oracle:
     """Sequential slab-hash map: B buckets, M elements per slab, hash multipliers (a, b)."""
 
     def __init__(self, num_buckets: int, slab_elems: int, hash_a: int, hash_b: int,
-                 pool_slabs: int | None = None):
+                 pool_slabs: int | None = None, duplicates: bool = False):
         self._l = _load()
         self.B, self.M = int(num_buckets), int(slab_elems)
         self.a, self.b = int(hash_a), int(hash_b)
@@ -95,6 +98,8 @@ class Oracle:
         self._t = self._l.om_create(self.B, self.M, self.a, self.b, cap)
         if not self._t:
             raise ValueError("invalid oracle parameters")
+        self.duplicates = bool(duplicates)
+        self._l.om_set_duplicates(self._t, int(self.duplicates))
 
     def __del__(self):
         t = getattr(self, "_t", None)
@@ -170,6 +175,26 @@ class Oracle:
         v = np.empty(n, np.uint32)
         self._l.om_dump(self._t, _ptr(b), _ptr(k), _ptr(v), n)
         return b, k, v
+
+    def delete_all(self, keys) -> np.ndarray:
+        """DELETEALL of each key in order; the number of elements each removed."""
+        k = _u32(keys)
+        c = np.empty(k.size, np.uint32)
+        self._l.om_delete_all_batch(self._t, _ptr(k), k.size, _ptr(c))
+        return c
+
+    def search_all(self, keys):
+        """SEARCHALL of each key: (counts, offsets, values), query i's values (in list order)
+        being values[offsets[i] : offsets[i] + counts[i]]."""
+        k = _u32(keys)
+        c = np.empty(k.size, np.uint32)
+        self._l.om_search_all_batch(self._t, _ptr(k), k.size, _ptr(c), None, None)
+        off = np.zeros(k.size, np.uint64)
+        if k.size:
+            off[1:] = np.cumsum(c[:-1], dtype=np.uint64)
+        v = np.empty(max(1, int(c.sum(dtype=np.uint64))), np.uint32)
+        self._l.om_search_all_batch(self._t, _ptr(k), k.size, _ptr(c), _ptr(off), _ptr(v))
+        return c, off, v[: int(c.sum(dtype=np.uint64))]
 
     def flush_all(self) -> None:
         self._l.om_flush_all(self._t)

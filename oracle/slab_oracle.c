@@ -19,9 +19,17 @@
  *     Not found is a no-op.
  *   - SEARCH(k): return the value of the live element with key k, or not-found ("Search").
  *
- * Because deleted spots keep their place and the list only grows at its tail, a bucket's
- * elements are kept here as one array in insertion order; slab j of the list holds array entries
- * [jM, (j+1)M). Slabs per bucket = max(1, ceil(occupied / M)), the base slab always existing.
+ * With duplicates allowed (om_set_duplicates; "Supported Operations": the multiset variants):
+ *   - INSERT(k, v): put (k, v) in the first empty spot from the head, with no uniqueness check
+ *     ("Insertion": INSERT), appending a slab when no spot is empty.
+ *   - DELETE(k): the first live element with key k from the head becomes an empty spot, which a
+ *     later INSERT may fill ("Deletion": with duplicates a deleted element is marked empty).
+ *   - SEARCH(k): the first live element with key k from the head.
+ *   - DELETEALL(k) / SEARCHALL(k): every live element with key k, in list order, in both modes.
+ *
+ * A bucket's spots are kept here as one array in list order (deleted spots keep their place;
+ * with duplicates allowed, emptied spots stay in the array until INSERT fills them); slab j of
+ * the list holds array entries [jM, (j+1)M). Slabs per bucket = max(1, ceil(occupied / M)), the base slab always existing.
  * Memory utilisation follows the formula of the "Slab Hash" subsection:
  *   u = x / (M x + y) * n / sum_i k_i,  x = element bytes, y = pointer (and aux) bytes.
  *
@@ -41,15 +49,17 @@
 #define OM_ERR_RESERVED 1u
 #define OM_ERR_NOMEM 2u
 
+enum { OM_DELETED = 0, OM_LIVE = 1, OM_HOLE = 2 };
+
 typedef struct {
     uint32_t key;
     uint32_t val;
-    uint32_t live; /* 1 = live element, 0 = deleted (tombstone) */
+    uint32_t live; /* OM_LIVE, OM_DELETED (kept, never reused) or OM_HOLE (empty, reusable) */
 } om_slot;
 
 typedef struct {
     om_slot *s;
-    uint32_t n;   /* occupied spots (live + deleted) */
+    uint32_t n;   /* spots in use or once used: live, deleted and holes */
     uint32_t cap;
 } om_bucket;
 
@@ -59,6 +69,7 @@ typedef struct {
     uint64_t pool_cap;  /* slabs available beyond the base slabs; UINT64_MAX = unbounded */
     uint64_t pool_used; /* slabs in use beyond the base slabs */
     uint32_t err;
+    uint32_t dup; /* 1 = duplicates allowed (multiset operations) */
     om_bucket *bk;
 } om_table;
 
@@ -102,6 +113,10 @@ void om_destroy(om_table *t)
 
 uint32_t om_error(const om_table *t) { return t->err; }
 
+/* Choose the operation set before any operation: 0 = unique keys (REPLACE, deleted spots kept),
+   1 = duplicates allowed (INSERT, deleted spots become empty). */
+void om_set_duplicates(om_table *t, uint32_t on) { t->dup = on ? 1u : 0u; }
+
 static uint32_t slabs_for(uint32_t occ, uint32_t M)
 {
     return occ == 0 ? 1u : (occ + M - 1) / M;
@@ -111,10 +126,12 @@ static uint32_t slabs_for(uint32_t occ, uint32_t M)
 static int64_t find_live(const om_bucket *bk, uint32_t k)
 {
     for (uint32_t i = 0; i < bk->n; i++)
-        if (bk->s[i].live && bk->s[i].key == k)
+        if (bk->s[i].live == OM_LIVE && bk->s[i].key == k)
             return (int64_t)i;
     return -1;
 }
+
+static int append(om_table *t, om_bucket *bk, uint32_t k, uint32_t v);
 
 /* REPLACE(k, v). */
 int om_replace(om_table *t, uint32_t k, uint32_t v)
@@ -129,6 +146,30 @@ int om_replace(om_table *t, uint32_t k, uint32_t v)
         bk->s[i].val = v;
         return 2;
     }
+    return append(t, bk, k, v);
+}
+
+/* INSERT(k, v) with duplicates allowed: the first empty spot from the head, else the tail. */
+int om_insert(om_table *t, uint32_t k, uint32_t v)
+{
+    if (k == OM_RESERVED) {
+        t->err |= OM_ERR_RESERVED;
+        return 0;
+    }
+    om_bucket *bk = &t->bk[om_bucket_of(t, k)];
+    for (uint32_t i = 0; i < bk->n; i++)
+        if (bk->s[i].live == OM_HOLE) {
+            bk->s[i].key = k;
+            bk->s[i].val = v;
+            bk->s[i].live = OM_LIVE;
+            return 1;
+        }
+    return append(t, bk, k, v);
+}
+
+/* Put (k, v) in the spot after the last used one. */
+static int append(om_table *t, om_bucket *bk, uint32_t k, uint32_t v)
+{
     /* Not present: the first empty spot is the next one in insertion order. When every spot of
        the list's slabs is occupied (the tail slab is full) a new slab is linked at the tail. */
     if (bk->n > 0 && bk->n % t->M == 0) {
@@ -148,12 +189,13 @@ int om_replace(om_table *t, uint32_t k, uint32_t v)
     }
     bk->s[bk->n].key = k;
     bk->s[bk->n].val = v;
-    bk->s[bk->n].live = 1;
+    bk->s[bk->n].live = OM_LIVE;
     bk->n++;
     return 1;
 }
 
-/* DELETE(k): mark as deleted; the spot stays occupied. */
+/* DELETE(k): mark as deleted; the spot stays occupied (unique keys) or becomes empty
+   (duplicates allowed). */
 int om_delete(om_table *t, uint32_t k)
 {
     if (k == OM_RESERVED) {
@@ -164,8 +206,44 @@ int om_delete(om_table *t, uint32_t k)
     int64_t i = find_live(bk, k);
     if (i < 0)
         return 0;
-    bk->s[i].live = 0;
+    bk->s[i].live = t->dup ? OM_HOLE : OM_DELETED;
     return 1;
+}
+
+/* DELETEALL(k): every live element with key k, as DELETE does each. Returns how many. */
+uint32_t om_delete_all(om_table *t, uint32_t k)
+{
+    if (k == OM_RESERVED) {
+        t->err |= OM_ERR_RESERVED;
+        return 0;
+    }
+    om_bucket *bk = &t->bk[om_bucket_of(t, k)];
+    uint32_t c = 0;
+    for (uint32_t i = 0; i < bk->n; i++)
+        if (bk->s[i].live == OM_LIVE && bk->s[i].key == k) {
+            bk->s[i].live = t->dup ? OM_HOLE : OM_DELETED;
+            c++;
+        }
+    return c;
+}
+
+/* SEARCHALL(k): the values of every live element with key k, in list order. Returns how many
+   there are (writes at most cap). */
+uint32_t om_search_all(const om_table *t, uint32_t k, uint32_t *vals, uint32_t cap)
+{
+    if (k == OM_RESERVED) {
+        ((om_table *)t)->err |= OM_ERR_RESERVED;
+        return 0;
+    }
+    const om_bucket *bk = &t->bk[om_bucket_of(t, k)];
+    uint32_t c = 0;
+    for (uint32_t i = 0; i < bk->n; i++)
+        if (bk->s[i].live == OM_LIVE && bk->s[i].key == k) {
+            if (c < cap)
+                vals[c] = bk->s[i].val;
+            c++;
+        }
+    return c;
 }
 
 /* SEARCH(k). *slabs_visited (if not NULL) receives the number of slabs a head-to-tail walk
@@ -202,7 +280,7 @@ void om_flush_buckets(om_table *t, uint32_t first, uint32_t count)
         om_bucket *bk = &t->bk[i];
         uint32_t before = slabs_for(bk->n, t->M), w = 0;
         for (uint32_t r = 0; r < bk->n; r++)
-            if (bk->s[r].live)
+            if (bk->s[r].live == OM_LIVE)
                 bk->s[w++] = bk->s[r];
         bk->n = w;
         t->pool_used -= before - slabs_for(bk->n, t->M);
@@ -217,11 +295,12 @@ void om_flush_all(om_table *t)
 
 /* ---- batched drivers: apply ops one after another in array order ---- */
 
+/* REPLACE (INSERT with duplicates allowed) of each pair in order. */
 void om_replace_batch(om_table *t, const uint32_t *keys, const uint32_t *vals, uint64_t n,
                       uint8_t *status)
 {
     for (uint64_t i = 0; i < n; i++) {
-        int s = om_replace(t, keys[i], vals[i]);
+        int s = t->dup ? om_insert(t, keys[i], vals[i]) : om_replace(t, keys[i], vals[i]);
         if (status)
             status[i] = (uint8_t)s;
     }
@@ -250,7 +329,7 @@ void om_search_batch(const om_table *t, const uint32_t *keys, uint64_t n, uint32
     }
 }
 
-/* ops: 0 = search, 1 = replace, 2 = delete. vals_out gets the search result (0xFFFFFFFF for
+/* ops: 0 = search, 1 = replace (INSERT with duplicates allowed), 2 = delete. vals_out gets the search result (0xFFFFFFFF for
    non-search ops and misses); status gets found / replace / delete status. */
 void om_mixed_batch(om_table *t, const uint8_t *ops, const uint32_t *keys,
                     const uint32_t *vals_in, uint64_t n, uint32_t *vals_out, uint8_t *status)
@@ -263,7 +342,7 @@ void om_mixed_batch(om_table *t, const uint8_t *ops, const uint32_t *keys,
             s = om_search(t, keys[i], &v, NULL);
             break;
         case 1:
-            s = om_replace(t, keys[i], vals_in[i]);
+            s = t->dup ? om_insert(t, keys[i], vals_in[i]) : om_replace(t, keys[i], vals_in[i]);
             break;
         case 2:
             s = om_delete(t, keys[i]);
@@ -279,21 +358,23 @@ void om_mixed_batch(om_table *t, const uint8_t *ops, const uint32_t *keys,
 
 /* ---- structure accounting ---- */
 
-/* Per-bucket live, deleted and slab counts (arrays of length B, any may be NULL). Returns the
-   total live count. */
+/* Per-bucket live, deleted and slab counts (arrays of length B, any may be NULL); empty spots
+   left by deletions with duplicates allowed count as neither. Returns the total live count. */
 uint64_t om_bucket_stats(const om_table *t, uint32_t *live, uint32_t *tomb, uint32_t *slabs)
 {
     uint64_t total = 0;
     for (uint32_t i = 0; i < t->B; i++) {
         const om_bucket *bk = &t->bk[i];
-        uint32_t l = 0;
-        for (uint32_t r = 0; r < bk->n; r++)
-            l += bk->s[r].live;
+        uint32_t l = 0, d = 0;
+        for (uint32_t r = 0; r < bk->n; r++) {
+            l += bk->s[r].live == OM_LIVE;
+            d += bk->s[r].live == OM_DELETED;
+        }
         total += l;
         if (live)
             live[i] = l;
         if (tomb)
-            tomb[i] = bk->n - l;
+            tomb[i] = d;
         if (slabs)
             slabs[i] = slabs_for(bk->n, t->M);
     }
@@ -327,7 +408,7 @@ uint64_t om_dump(const om_table *t, uint32_t *bucket, uint32_t *key, uint32_t *v
     for (uint32_t i = 0; i < t->B; i++) {
         const om_bucket *bk = &t->bk[i];
         for (uint32_t r = 0; r < bk->n; r++) {
-            if (!bk->s[r].live)
+            if (bk->s[r].live != OM_LIVE)
                 continue;
             if (c < cap) {
                 bucket[c] = i;
@@ -338,6 +419,22 @@ uint64_t om_dump(const om_table *t, uint32_t *bucket, uint32_t *key, uint32_t *v
         }
     }
     return c;
+}
+
+void om_delete_all_batch(om_table *t, const uint32_t *keys, uint64_t n, uint32_t *counts)
+{
+    for (uint64_t i = 0; i < n; i++)
+        counts[i] = om_delete_all(t, keys[i]);
+}
+
+/* SEARCHALL of each key in order: counts[i] values of query i go to vals[offsets[i] ...] when
+   vals is not NULL (offsets from a previous counting call). */
+void om_search_all_batch(const om_table *t, const uint32_t *keys, uint64_t n, uint32_t *counts,
+                         const uint64_t *offsets, uint32_t *vals)
+{
+    for (uint64_t i = 0; i < n; i++)
+        counts[i] = om_search_all(t, keys[i], vals ? vals + offsets[i] : NULL,
+                                  vals ? 0xFFFFFFFFu : 0u);
 }
 
 void om_bucket_of_batch(const om_table *t, const uint32_t *keys, uint64_t n, uint32_t *out)

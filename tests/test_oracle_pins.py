@@ -79,6 +79,57 @@ class SlabListModel:
                     return 1, spot[1], j + 1
         return 0, EMPTY, len(slabs)
 
+    def insert(self, k, v):
+        """INSERT with duplicates allowed: the first empty spot from the head, else a new slab."""
+        if k == EMPTY:
+            self.err |= 1
+            return 0
+        for slab in self.lists[self.bucket_of(k)]:
+            for i, spot in enumerate(slab):
+                if spot is None:
+                    slab[i] = [k, v, True]
+                    return 1
+        if self.pool is not None and self.pool_used >= self.pool:
+            self.err |= 2
+            return 0
+        self.lists[self.bucket_of(k)].append([[k, v, True]] + [None] * (self.M - 1))
+        self.pool_used += 1
+        return 1
+
+    def delete_dup(self, k):
+        """DELETE with duplicates allowed: the first live match from the head becomes empty."""
+        if k == EMPTY:
+            self.err |= 1
+            return 0
+        for slab in self.lists[self.bucket_of(k)]:
+            for i, spot in enumerate(slab):
+                if spot is not None and spot[2] and spot[0] == k:
+                    slab[i] = None
+                    return 1
+        return 0
+
+    def delete_all(self, k, dup):
+        if k == EMPTY:
+            self.err |= 1
+            return 0
+        c = 0
+        for slab in self.lists[self.bucket_of(k)]:
+            for i, spot in enumerate(slab):
+                if spot is not None and spot[2] and spot[0] == k:
+                    if dup:
+                        slab[i] = None
+                    else:
+                        spot[2] = False
+                    c += 1
+        return c
+
+    def search_all(self, k):
+        if k == EMPTY:
+            self.err |= 1
+            return []
+        return [spot[1] for slab in self.lists[self.bucket_of(k)] for spot in slab
+                if spot is not None and spot[2] and spot[0] == k]
+
     def flush(self, b):
         """Walk bucket b's slabs head to tail, keep the live spots in the order met, and lay them
         out again from the head, one slab per M spots (at least one slab); the slabs no longer
@@ -143,6 +194,56 @@ def test_oracle_matches_slab_list_model(oracle_mod, B, M):
         probe = np.arange(domain, dtype=np.uint32)
         _, _, visits = o.search(probe)
         assert [model.search(int(k))[2] for k in probe] == visits.tolist()
+
+
+@pytest.mark.parametrize("dup", [True, False])
+@pytest.mark.parametrize("B,M", [(1, 1), (1, 3), (2, 2), (3, 31), (5, 2)])
+def test_oracle_multiset_ops_match_slab_list_model(oracle_mod, B, M, dup):
+    """INSERT / DELETE / SEARCH with duplicates allowed, and DELETEALL / SEARCHALL in both modes,
+    op by op against the literal model on small key domains (many repeated keys), with flushes
+    in between; stats, pool count, live multiset and search visits after each segment."""
+    rng = W.SplitMix64(3000 + 10 * B + M + (7 if dup else 0))
+    for trial in range(20):
+        pool = None if trial % 4 else 3
+        a, b = W.hash_params(rng, oracle_mod.PRIME)
+        o = oracle_mod.Oracle(B, M, a, b, pool_slabs=pool, duplicates=dup)
+        model = SlabListModel(lambda k: int(o.bucket_of([k])[0]), B, M, pool)
+        domain = int(rng.below(1, 6)[0]) + 2
+        for seg in range(4):
+            n_ops = 60
+            kinds = rng.below(n_ops, 5)
+            keys = rng.below(n_ops, domain).astype(np.uint32)
+            keys[rng.below(n_ops, 50) == 0] = EMPTY
+            vals = (rng.next(n_ops) >> np.uint64(32)).astype(np.uint32)
+            for i in range(n_ops):
+                k, v, kind = int(keys[i]), int(vals[i]), int(kinds[i])
+                kk = keys[i:i + 1]
+                if kind == 0:
+                    gv, gf, gvis = o.search(kk)
+                    f, mv, vis = model.search(k)
+                    assert (int(gf[0]), int(gv[0]), int(gvis[0])) == (f, mv, vis), (trial, i)
+                elif kind == 1:
+                    want = model.insert(k, v) if dup else model.replace(k, v)
+                    assert int(o.replace(kk, vals[i:i + 1])[0]) == want, (trial, i)
+                elif kind == 2:
+                    want = model.delete_dup(k) if dup else model.delete(k)
+                    assert int(o.delete(kk)[0]) == want, (trial, i)
+                elif kind == 3:
+                    assert int(o.delete_all(kk)[0]) == model.delete_all(k, dup), (trial, i)
+                else:
+                    c, off, vv = o.search_all(kk)
+                    assert vv.tolist() == model.search_all(k) and int(c[0]) == vv.size
+            o.flush(seg % B, 1)
+            model.flush(seg % B)
+            live, tomb, slabs = o.bucket_stats()
+            ml, mt, ms = model.stats()
+            assert list(live) == ml and list(tomb) == mt and list(slabs) == ms, (trial, seg)
+            assert o.pool_used == model.pool_used == sum(s - 1 for s in ms)
+            assert o.error == model.err
+            db, dk, dv = o.dump()
+            assert sorted(zip(db.tolist(), dk.tolist(), dv.tolist())) == model.dump()
+        if dup:
+            assert tomb.sum() == 0       # with duplicates a deletion leaves an empty spot
 
 
 @pytest.mark.parametrize("B,M", [(1, 2), (3, 1), (3, 3), (5, 2)])
