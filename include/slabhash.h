@@ -61,11 +61,19 @@ enum { SH_ERR_RESERVED_KEY = 1u, SH_ERR_POOL_EXHAUSTED = 2u };
 #define SH_BLOCK_SLABS 2048u /* pool slabs per allocator block (one 256-byte bitmap) */
 
 /* Table geometry and hash ("Slab Hash" subsection): bucket(k) = ((a k + b) mod p) mod B. */
+/* Table flags ("Supported Operations"): with SH_TABLE_DUPLICATES the table is a multiset: an
+   insert adds its pair without looking for the key (INSERT, not REPLACE), and a delete turns the
+   first matching slot into an empty slot that later inserts may fill (the paper's deletion when
+   duplicates are allowed). Without it keys are unique (REPLACE) and deleted slots stay
+   tombstones. Searches return the first match in list order in both modes. */
+enum { SH_TABLE_DUPLICATES = 1u };
+
 typedef struct {
     uint32_t num_buckets; /* B >= 1 */
     uint32_t pool_slabs;  /* slabs beyond the base slabs; a multiple of SH_BLOCK_SLABS, may be 0 */
     uint32_t hash_a;      /* 1 <= a < p */
     uint32_t hash_b;      /* 0 <= b < p */
+    uint32_t flags;       /* 0 or SH_TABLE_DUPLICATES; other bits are invalid */
 } sh_params_t;
 
 /* Launch shape of the operation kernels. Never changes results.
@@ -153,7 +161,9 @@ sh_status_t sh_set_launch(sh_table_t *t, const sh_launch_t *shape);
 /* Bulk build: insert n pairs, each lane of a wavefront holding one ("Bulk benchmarks"; the
    paper notes a bulk build and an incremental batch insertion are the same operation). Uses
    REPLACE semantics ("Supported Operations": replace the value of an existing key, else insert
-   at the first empty slot, linking a new slab when the tail is full). d_status may be NULL. */
+   at the first empty slot, linking a new slab when the tail is full); on a table with
+   SH_TABLE_DUPLICATES, INSERT semantics (the first empty slot from the head, status always 1
+   unless the pool is exhausted). d_status may be NULL. */
 sh_status_t sh_build(sh_table_t *t, const uint32_t *d_keys, const uint32_t *d_vals, uint64_t n,
                      uint8_t *d_status, void *stream);
 
@@ -162,8 +172,9 @@ sh_status_t sh_build(sh_table_t *t, const uint32_t *d_keys, const uint32_t *d_va
 sh_status_t sh_insert(sh_table_t *t, const uint32_t *d_keys, const uint32_t *d_vals,
                       uint64_t n, uint8_t *d_status, void *stream);
 
-/* DELETE ("Deletion" subsection): the matching slot becomes a tombstone (never empty again, so
-   not reused). Absent keys give status 0. d_status may be NULL. */
+/* DELETE ("Deletion" subsection): the first matching slot in list order becomes a tombstone
+   (never empty again, so not reused), or on a table with SH_TABLE_DUPLICATES an empty slot.
+   Absent keys give status 0. d_status may be NULL. */
 sh_status_t sh_delete(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint8_t *d_status,
                       void *stream);
 
@@ -179,6 +190,23 @@ sh_status_t sh_search(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint32_
 sh_status_t sh_mixed(sh_table_t *t, const uint8_t *d_ops, const uint32_t *d_keys,
                      const uint32_t *d_vals_in, uint64_t n, uint32_t *d_vals_out,
                      uint8_t *d_status, void *stream);
+
+/* SEARCHALL ("Supported Operations"; "Search": the whole list is searched): for each key, every
+   live element with that key, in list order. d_counts[i] receives how many there are. With
+   d_offsets and d_vals_out (both or neither), query i's values also go to d_vals_out[d_offsets[i]],
+   d_vals_out[d_offsets[i] + 1], ..., but never past d_offsets[i + 1] (d_vals_cap for the last
+   query): a caller sizes the output from the counts of a first call without them (their
+   exclusive prefix sum gives the offsets), and a table changed in between cannot make a query
+   write outside its range. Reads through caches, like sh_search. */
+sh_status_t sh_search_all(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint32_t *d_counts,
+                          const uint64_t *d_offsets, uint32_t *d_vals_out, uint64_t d_vals_cap,
+                          void *stream);
+
+/* DELETEALL ("Supported Operations"; "Deletion": the whole list is processed): every live
+   element with the key is deleted as sh_delete deletes one (a tombstone, or an empty slot with
+   SH_TABLE_DUPLICATES). d_counts[i] (may be NULL) receives how many this call deleted. */
+sh_status_t sh_delete_all(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint32_t *d_counts,
+                          void *stream);
 
 /* Walk every bucket and return totals, allocator occupancy and the error word in *h_out.
    Synchronises `stream`. */
@@ -218,7 +246,8 @@ typedef struct sh_graph sh_graph_t;
 size_t sh_multi_storage_bytes(uint32_t T, const sh_params_t *h_params);
 
 /* Bind T tables to caller-owned storage (256-byte aligned, at least sh_multi_storage_bytes) and
-   enqueue their initialisation and the directory upload on `stream`. */
+   enqueue their initialisation and the directory upload on `stream`. The batched kernel runs
+   the unique-key operations: tables with SH_TABLE_DUPLICATES give SH_EINVAL. */
 sh_status_t sh_multi_create(uint32_t T, const sh_params_t *h_params, void *d_storage,
                             size_t bytes, void *stream, sh_multi_t **out);
 
@@ -299,7 +328,8 @@ size_t sh_server_scratch_bytes(const sh_server_cfg_t *cfg);
 
 /* Start serving table t. d_scratch: caller-owned device memory (256-byte aligned, at least
    sh_server_scratch_bytes). Synchronises `stream` once to read the pool occupancy. No other call
-   may use the table while the server runs. */
+   may use the table while the server runs. A table with SH_TABLE_DUPLICATES gives SH_EINVAL
+   (requests run through the batched kernel). */
 sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uint8_t *d_ops,
                             const uint32_t *d_keys, const uint32_t *d_vals_in,
                             uint32_t *d_vals_out, uint8_t *d_status, uint64_t n_ops,

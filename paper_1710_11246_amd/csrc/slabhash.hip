@@ -63,6 +63,7 @@ struct View {
     Header *hdr;
     unsigned long long *counters; // kCounterSlots x 8
     uint32_t B, a, b, pool_slabs, nblk;
+    uint32_t dup; // 1 = duplicates allowed (SH_TABLE_DUPLICATES)
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -269,7 +270,7 @@ struct WaveLds {
 
 // One chunk of up to 64 ops (lane l < count holds op base + l) on table T, processed in rounds
 // until every op has finished (see the description above).
-template <int K>
+template <int K, bool Dup>
 __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
                           const uint8_t *__restrict__ ops, const uint32_t *__restrict__ keys,
                           const uint32_t *__restrict__ vals, uint32_t *__restrict__ vout,
@@ -325,8 +326,10 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
             const uint64_t w = pre[q];
             const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
             const uint32_t kq = L.key[2 * q + half];
-            const bool is_key = !is31 && lo == kq;
-            const uint32_t kh = (uint32_t)(ballot(is_key) >> hshift); // my half's key votes
+            const bool match = !is31 && lo == kq;
+            const uint32_t kh = (uint32_t)(ballot(match) >> hshift); // my half's key votes
+            // the op's slot is the first match of the slab (with unique keys the only one)
+            const bool is_key = Dup ? (match && (kh & below) == 0u) : match;
             bool ins = (K == kInsert);
             uint32_t code_key = (K == kSearch) ? kMsgFound
                                                : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
@@ -343,11 +346,14 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
                 const uint32_t eh = (uint32_t)(ballot(is_empty) >> hshift);
                 const bool first_empty = ins && is_empty && (eh & below) == 0u;
                 const bool tail = is31 && (!ins || eh == 0u);
-                target = is_key || (kh == 0u && (first_empty || tail));
-                code = is_key ? code_key
-                              : (first_empty ? kMsgSwapIns
-                                             : (hi != kEmpty ? kMsgMove
-                                                             : (ins ? kMsgGrow : kMsgEnd)));
+                // with duplicates an insert takes the first empty slot whatever keys it meets
+                const bool hit = Dup ? (is_key && !ins) : is_key;
+                const uint32_t khe = (Dup && ins) ? 0u : kh;
+                target = hit || (khe == 0u && (first_empty || tail));
+                code = hit ? code_key
+                           : (first_empty ? kMsgSwapIns
+                                          : (hi != kEmpty ? kMsgMove
+                                                          : (ins ? kMsgGrow : kMsgEnd)));
             } else {
                 target = is_key || (kh == 0u && is31);
                 code = is_key ? code_key : (hi != kEmpty ? kMsgMove : kMsgEnd);
@@ -375,17 +381,20 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
             if (code >= kMsgSwapIns) {
                 uint32_t cslot = tslot;
                 uint64_t *slab = T.base + (size_t)((loc == kEmpty) ? bkt : T.B + loc) * 32;
-                const uint64_t desired =
-                    (code == kMsgSwapDel) ? kTombPair : (((uint64_t)val << 32) | key);
+                // a delete leaves a tombstone, or with duplicates an empty slot
+                const uint64_t desired = (code == kMsgSwapDel)
+                                             ? (Dup ? kEmptyPair : kTombPair)
+                                             : (((uint64_t)val << 32) | key);
                 uint64_t expect = (code == kMsgSwapIns) ? kEmptyPair
                                                         : (((uint64_t)payload << 32) | key);
                 uint64_t old = cas64(slab + cslot, expect, desired);
                 if (old == expect) {
                     rs = (code == kMsgSwapRep) ? 2u : 1u;
                     won = true;
-                } else if (code == kMsgSwapIns) {
+                } else if (code == kMsgSwapIns && !Dup) {
                     // Walk forward from the lost empty slot using the occupants the swaps
-                    // return; at most the 31 slots of this slab.
+                    // return; at most the 31 slots of this slab. (With duplicates, empty slots
+                    // need not be a suffix, so a lost insert re-reads its slab next round.)
                     for (;;) {
                         if ((uint32_t)old == key) { // the same key was inserted: replace it
                             expect = old;
@@ -485,7 +494,7 @@ __device__ __forceinline__ void alloc_init(Alloc &al, uint32_t wave, uint32_t se
     al.rot = mix32(al.start) & 63u;
 }
 
-template <int K>
+template <int K, bool Dup>
 __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__restrict__ ops,
                                                      const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ vals,
@@ -504,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__re
     for (uint64_t c = wave; c < nchunks; c += nwaves) {
         const uint64_t base = c * C;
         const uint32_t count = (uint32_t)((n - base < C) ? n - base : C);
-        run_chunk<K>(T, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base, count, flags);
+        run_chunk<K, Dup>(T, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base, count, flags);
     }
     if (flags & kFlagCounters)
         flush_counters(T, cnt, al, wave);
@@ -592,8 +601,8 @@ __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ 
             count = 0; // range outside the op arrays: nothing is read or written
         else if (count > n_ops - base)
             count = n_ops - base;
-        run_chunk<kMixed>(Tv, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base,
-                          (uint32_t)count, flags);
+        run_chunk<kMixed, false>(Tv, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base,
+                                 (uint32_t)count, flags);
     }
     if ((flags & kFlagCounters) && cur_t != kEmpty)
         flush_counters(dir[cur_t], cnt, al, wave);
@@ -635,8 +644,8 @@ __global__ __launch_bounds__(kBlock) void walk_kernel(View T, uint32_t *__restri
             nt += __popcll(Tm);
             if (bad)
                 ++viol;
-            if (E && E != (kSlotMask & ~((1ull << ffs0(E)) - 1)))
-                ++viol; // empty slots must form a suffix
+            if (!T.dup && E && E != (kSlotMask & ~((1ull << ffs0(E)) - 1)))
+                ++viol; // empty slots must form a suffix (with unique keys)
             const uint32_t aux = rl(lo, 31), next = rl(hi, 31);
             if (aux != kEmpty)
                 ++viol;
@@ -657,8 +666,8 @@ __global__ __launch_bounds__(kBlock) void walk_kernel(View T, uint32_t *__restri
             }
             if (next == kEmpty)
                 break;
-            if (E)
-                ++viol; // a slab with a successor must be full
+            if (E && !T.dup)
+                ++viol; // a slab with a successor must be full (with unique keys)
             if (next >= T.pool_slabs || !bitmap_has(T, next) || ns > T.pool_slabs) {
                 ++viol;
                 break;
@@ -768,6 +777,105 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
             if (lane == 0)
                 slab_free(T, f);
             f = nf;
+        }
+    }
+}
+
+// SEARCHALL and DELETEALL ("Supported Operations"): every live element with the key, in list
+// order, so each op walks its whole list. A wavefront holds a chunk of up to 64 ops, reads
+// their base slabs in one straight run (two ops per load, as in run_chunk), then takes the ops
+// a pair at a time: lanes 0..31 walk op 2q's list and lanes 32..63 op 2q+1's, each slab voted
+// on at once. SEARCHALL writes the values of the matching slots in list order from
+// offsets[op], never past `limit` of the op (the next op's offset, or the output's capacity);
+// DELETEALL swaps each matching slot to `gone` (a tombstone, or an empty slot with duplicates),
+// retrying a slot whose value a concurrent replace changed. counts[op] receives the number of
+// matches found (SEARCHALL) or deleted (DELETEALL).
+template <bool Del>
+__global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__restrict__ keys,
+                                                     uint64_t n, uint32_t *__restrict__ counts,
+                                                     const uint64_t *__restrict__ offsets,
+                                                     uint32_t *__restrict__ vout,
+                                                     uint64_t vcap, uint64_t gone)
+{
+    __shared__ uint32_t ku[kWavesPerBlock][2][64];
+    const uint32_t lane = lane_id();
+    const uint32_t half = lane >> 5, slot = lane & 31;
+    const uint32_t below = (1u << slot) - 1u;
+    const uint32_t wl_ = threadIdx.x >> 6;
+    const uint64_t wave = blockIdx.x * (uint64_t)kWavesPerBlock + wl_;
+    const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
+    const uint64_t nchunks = (n + 63) / 64;
+    uint32_t *kk = ku[wl_][0], *uu = ku[wl_][1];
+    for (uint64_t c = wave; c < nchunks; c += nwaves) {
+        const uint64_t base = c * 64;
+        const uint32_t count = (n - base < 64) ? (uint32_t)(n - base) : 64u;
+        const bool in = lane < count;
+        const uint32_t key = in ? keys[base + lane] : kEmpty;
+        const uint64_t res_m = ballot(in && key == kEmpty);
+        if (res_m)
+            raise_error(T, SH_ERR_RESERVED_KEY, lane, ffs0(res_m));
+        kk[lane] = key;
+        uu[lane] = (in && key != kEmpty) ? bucket_of(key, T.a, T.b, T.B) : 0u;
+        __builtin_amdgcn_wave_barrier();
+        uint64_t pre[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q)
+            pre[q] = load_slot<Del>(T.base + (size_t)uu[2 * q + half] * 32 + slot);
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            if (2 * (uint32_t)q >= count)
+                break;
+            const uint32_t op = 2 * q + half;
+            const uint32_t kq = kk[op];
+            bool go = op < count && kq != kEmpty;
+            uint64_t lim = 0, out0 = 0;
+            if (!Del && vout && go) {
+                out0 = offsets[base + op];
+                lim = (base + op + 1 < n) ? offsets[base + op + 1] : vcap;
+            }
+            uint64_t w = pre[q];
+            uint32_t u = uu[op], found = 0, steps = 0;
+            for (;;) {
+                const bool m = go && slot < 31 && (uint32_t)w == kq;
+                const uint32_t mm = (uint32_t)(ballot(m) >> (lane & 32u));
+                uint32_t hits = (uint32_t)__popc(mm);
+                if constexpr (Del) {
+                    bool ok = false;
+                    if (m) {
+                        uint64_t *p = T.base + (size_t)u * 32 + slot;
+                        uint64_t expect = w;
+                        for (;;) {
+                            const uint64_t old = cas64(p, expect, gone);
+                            if (old == expect) {
+                                ok = true;
+                                break;
+                            }
+                            if ((uint32_t)old != kq)
+                                break; // deleted by someone else meanwhile
+                            expect = old; // a replace changed the value: delete that
+                        }
+                    }
+                    hits = (uint32_t)__popc((uint32_t)(ballot(ok) >> (lane & 32u)));
+                } else {
+                    if (m && vout) {
+                        const uint64_t at = out0 + found + (uint32_t)__popc(mm & below);
+                        if (at < lim && at < vcap)
+                            vout[at] = (uint32_t)(w >> 32);
+                    }
+                }
+                found += hits;
+                const uint32_t nx = (uint32_t)__shfl((int)(uint32_t)(w >> 32),
+                                                     (int)((lane & 32u) | 31u), 64);
+                go = go && nx != kEmpty && nx < T.pool_slabs && ++steps <= T.pool_slabs;
+                if (!ballot(go))
+                    break;
+                if (go) {
+                    u = T.B + nx;
+                    w = load_slot<Del>(T.base + (size_t)u * 32 + slot);
+                }
+            }
+            if (slot == 0 && op < count && counts)
+                counts[base + op] = found;
         }
     }
 }
@@ -904,7 +1012,8 @@ bool layout_of(const sh_params_t *p, Layout *L)
 {
     if (!p || p->num_buckets == 0 || p->pool_slabs % SH_BLOCK_SLABS != 0 || p->hash_a == 0 ||
         p->hash_a >= kPrime || p->hash_b >= kPrime ||
-        (uint64_t)p->num_buckets + p->pool_slabs >= 0xFFFFFFFFull)
+        (uint64_t)p->num_buckets + p->pool_slabs >= 0xFFFFFFFFull ||
+        (p->flags & ~(uint32_t)SH_TABLE_DUPLICATES) != 0)
         return false;
     L->base = kHeaderBytes;
     L->pool = L->base + (size_t)p->num_buckets * SH_SLAB_BYTES;
@@ -973,8 +1082,14 @@ sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
     if (n >= (1ull << 32) || !keys)
         return SH_EINVAL;
     const uint32_t C = ops_per_wave_for(t, n);
-    hipLaunchKernelGGL(ops_kernel<K>, dim3(grid_for(t, n, C)), dim3(kBlock), 0, S(stream), t->v,
-                       ops, keys, vals, n, vout, sout, t->seq++, C, t->flags);
+    if (t->v.dup)
+        hipLaunchKernelGGL((ops_kernel<K, true>), dim3(grid_for(t, n, C)), dim3(kBlock), 0,
+                           S(stream), t->v, ops, keys, vals, n, vout, sout, t->seq++, C,
+                           t->flags);
+    else
+        hipLaunchKernelGGL((ops_kernel<K, false>), dim3(grid_for(t, n, C)), dim3(kBlock), 0,
+                           S(stream), t->v, ops, keys, vals, n, vout, sout, t->seq++, C,
+                           t->flags);
     return check_launch();
 }
 
@@ -1044,6 +1159,7 @@ void bind_table(sh_table *t, const sh_params_t *p, char *storage, size_t bytes, 
     t->v.b = p->hash_b;
     t->v.pool_slabs = p->pool_slabs;
     t->v.nblk = p->pool_slabs / SH_BLOCK_SLABS;
+    t->v.dup = (p->flags & SH_TABLE_DUPLICATES) ? 1u : 0u;
 }
 
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1057,8 +1173,8 @@ size_t multi_layout(uint32_t T, const sh_params_t *p, size_t *offs)
     size_t off = round256((size_t)T * sizeof(View));
     for (uint32_t t = 0; t < T; ++t) {
         Layout L;
-        if (!layout_of(&p[t], &L))
-            return 0;
+        if (!layout_of(&p[t], &L) || (p[t].flags & SH_TABLE_DUPLICATES))
+            return 0; // the batched kernel runs the unique-key operations only
         if (offs)
             offs[t] = off;
         off += round256(L.total);
@@ -1158,6 +1274,48 @@ sh_status_t sh_flush(sh_table_t *t, uint32_t first_bucket, uint32_t num_buckets,
     hipLaunchKernelGGL(flush_kernel, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
                        first_bucket, num_buckets);
     return check_launch();
+}
+
+static sh_status_t launch_all(sh_table *t, bool del, const uint32_t *keys, uint64_t n,
+                              uint32_t *counts, const uint64_t *offsets, uint32_t *vals,
+                              uint64_t cap, void *stream)
+{
+    uint64_t waves = (uint64_t)t->num_cu * t->waves_per_cu;
+    const uint64_t chunks = (n + 63) / 64;
+    if (waves > chunks)
+        waves = chunks;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (del)
+        hipLaunchKernelGGL(all_kernel<true>, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
+                           keys, n, counts, nullptr, nullptr, 0,
+                           t->v.dup ? kEmptyPair : kTombPair);
+    else
+        hipLaunchKernelGGL(all_kernel<false>, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
+                           keys, n, counts, offsets, vals, cap, 0);
+    return check_launch();
+}
+
+sh_status_t sh_search_all(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint32_t *d_counts,
+                          const uint64_t *d_offsets, uint32_t *d_vals_out, uint64_t d_vals_cap,
+                          void *stream)
+{
+    if (!t || n >= (1ull << 32) || (n && (!d_keys || !d_counts)) ||
+        (d_offsets == nullptr) != (d_vals_out == nullptr))
+        return SH_EINVAL;
+    if (n == 0)
+        return SH_OK;
+    return launch_all(t, false, d_keys, n, d_counts, d_offsets, d_vals_out,
+                      d_vals_out ? d_vals_cap : 0, stream);
+}
+
+sh_status_t sh_delete_all(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint32_t *d_counts,
+                          void *stream)
+{
+    if (!t || n >= (1ull << 32) || (n && !d_keys))
+        return SH_EINVAL;
+    if (n == 0)
+        return SH_OK;
+    return launch_all(t, true, d_keys, n, d_counts, nullptr, nullptr, 0, stream);
 }
 
 sh_status_t sh_alloc_slabs(sh_table_t *t, uint64_t n, uint32_t *d_out, void *stream)
@@ -1728,7 +1886,7 @@ sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uin
     const size_t need = sh_server_scratch_bytes(&c);
     if (!t || !out || !d_ops || !d_keys || !d_vals_in || !d_vals_out || !d_status ||
         n_ops == 0 || n_ops >= (1ull << 40) || !d_scratch || need == 0 ||
-        scratch_bytes < need || (reinterpret_cast<uintptr_t>(d_scratch) & 255u))
+        scratch_bytes < need || (reinterpret_cast<uintptr_t>(d_scratch) & 255u) || t->v.dup)
         return SH_EINVAL;
     sh_server *s = new (std::nothrow) sh_server();
     if (!s)

@@ -32,9 +32,13 @@ SH_BLOCK_SLABS = 2048
 SH_MAX_BATCHES = 4096
 
 
+SH_TABLE_DUPLICATES = 1
+
+
 class ShParams(ctypes.Structure):
     _fields_ = [("num_buckets", ctypes.c_uint32), ("pool_slabs", ctypes.c_uint32),
-                ("hash_a", ctypes.c_uint32), ("hash_b", ctypes.c_uint32)]
+                ("hash_a", ctypes.c_uint32), ("hash_b", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
 
 
 SH_LAUNCH_COUNTERS = 1
@@ -80,6 +84,8 @@ _SIGS = {
     "sh_reset": ([_P, _P], ctypes.c_int),
     "sh_flush": ([_P, _U32, _U32, _P], ctypes.c_int),
     "sh_alloc_slabs": ([_P, _U64, _P, _P], ctypes.c_int),
+    "sh_search_all": ([_P, _P, _U64, _P, _P, _P, _U64, _P], ctypes.c_int),
+    "sh_delete_all": ([_P, _P, _U64, _P, _P], ctypes.c_int),
     "sh_free_slabs": ([_P, _P, _U64, _P], ctypes.c_int),
     "sh_destroy": ([_P], ctypes.c_int),
     "sh_set_launch": ([_P, _P], ctypes.c_int),
@@ -193,6 +199,24 @@ def sh_reset(t, stream=None) -> None:
 
 def sh_flush(t, first_bucket: int, num_buckets: int, stream=None) -> None:
     _check("sh_flush", lib().sh_flush(t, int(first_bucket), int(num_buckets), _stream(stream)))
+
+
+def sh_search_all(t, keys: torch.Tensor, counts: torch.Tensor, offsets=None, vals=None,
+                  stream=None) -> None:
+    n = keys.numel()
+    k = _dev(keys, "keys", _U32_TYPES, n)
+    c = _dev(counts, "counts", _U32_TYPES, n)
+    o = _dev(offsets, "offsets", (torch.int64,), n, allow_none=True)
+    v = _dev(vals, "vals", _U32_TYPES, None, allow_none=True)
+    cap = vals.numel() if vals is not None else 0
+    _check("sh_search_all", lib().sh_search_all(t, k, n, c, o, v, cap, _stream(stream)))
+
+
+def sh_delete_all(t, keys: torch.Tensor, counts=None, stream=None) -> None:
+    n = keys.numel()
+    k = _dev(keys, "keys", _U32_TYPES, n)
+    c = _dev(counts, "counts", _U32_TYPES, n, allow_none=True)
+    _check("sh_delete_all", lib().sh_delete_all(t, k, n, c, _stream(stream)))
 
 
 def sh_alloc_slabs(t, n: int, out: torch.Tensor, stream=None) -> None:
@@ -455,8 +479,9 @@ class SlabHash:
     a table owned by a MultiSlabHash)."""
 
     def __init__(self, num_buckets: int, pool_slabs: int, hash_a: int, hash_b: int,
-                 device="cuda", stream=None, handle=None, owner=None):
-        self.params = ShParams(int(num_buckets), int(pool_slabs), int(hash_a), int(hash_b))
+                 device="cuda", stream=None, handle=None, owner=None, duplicates: bool = False):
+        self.params = ShParams(int(num_buckets), int(pool_slabs), int(hash_a), int(hash_b),
+                               SH_TABLE_DUPLICATES if duplicates else 0)
         self.device = device
         self.owner = owner
         if handle is not None:
@@ -487,6 +512,29 @@ class SlabHash:
 
     def set_launch(self, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0):
         sh_set_launch(self.handle, waves_per_cu, ops_per_wave, flags)
+
+    def search_all(self, keys, stream=None):
+        """SEARCHALL of each key: (counts, offsets, values) as device tensors, query i's values
+        (in list order) being values[offsets[i] : offsets[i] + counts[i]]. Two calls: counts,
+        then the values into an output sized from them."""
+        n = keys.numel()
+        counts = torch.empty(n, dtype=torch.int32, device=keys.device)
+        sh_search_all(self.handle, keys, counts, stream=stream)
+        c64 = counts.to(torch.int64)
+        offsets = torch.zeros(n, dtype=torch.int64, device=keys.device)
+        if n > 1:
+            offsets[1:] = torch.cumsum(c64[:-1], 0)
+        total = int(c64.sum().item()) if n else 0
+        vals = torch.empty(max(total, 1), dtype=torch.int32, device=keys.device)
+        sh_search_all(self.handle, keys, counts, offsets, vals[:total] if total else vals[:1],
+                      stream=stream)
+        return counts, offsets, vals[:total]
+
+    def delete_all(self, keys, stream=None):
+        """DELETEALL of each key; the number of elements each removed (device tensor)."""
+        counts = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+        sh_delete_all(self.handle, keys, counts, stream=stream)
+        return counts
 
     def flush(self, first: int = 0, count: int | None = None, stream=None):
         """FLUSH of buckets [first, first + count) (every bucket from `first` by default)."""
@@ -525,8 +573,8 @@ class SlabHash:
         return sh_stats(self.handle, stream)
 
     def dump(self, stream=None):
-        """Returns numpy (bucket, key, value) sorted by (bucket, key), per-bucket counts [B, 3]
-        (live, deleted, slabs), and the violation count."""
+        """Returns numpy (bucket, key, value) sorted by (bucket, key, value), per-bucket counts
+        [B, 3] (live, deleted, slabs), and the violation count."""
         dev = self.device
         count = torch.zeros(1, dtype=torch.int64, device=dev)
         viol = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -539,7 +587,7 @@ class SlabHash:
         sh_dump(self.handle, b, k, v, counts, count, viol, stream)
         torch.cuda.synchronize()
         b, k, v = to_host_u32(b)[:n], to_host_u32(k)[:n], to_host_u32(v)[:n]
-        order = np.lexsort((k, b))
+        order = np.lexsort((v, k, b))
         return (b[order], k[order], v[order], to_host_u32(counts).reshape(-1, 3),
                 int(viol.item()))
 

@@ -1,0 +1,213 @@
+"""GPU parity of the multiset operations ("Supported Operations": INSERT, DELETE with duplicates,
+DELETEALL, SEARCH, SEARCHALL) against the oracle. Where concurrency leaves a choice (which
+empty slot a concurrent insert takes, which of several equal keys comes first in a list filled
+by one batch), the tests compare what is unique: the live multiset, per-bucket counts, counts
+per key; list order is checked where it is determined (copies inserted one per batch)."""
+import sys
+from collections import Counter
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1710_11246_amd import slabhash as S
+from paper_1710_11246_amd import workload as W
+
+from test_gpu_parity import M, assert_same_table
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    S.lib()
+
+
+def make_dup(oracle_mod, B, pool, seed):
+    rng = W.SplitMix64(seed)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    t = S.SlabHash(B, pool, a, b, duplicates=True)
+    o = oracle_mod.Oracle(B, M, a, b, duplicates=True)
+    return t, o, rng
+
+
+def per_key_sum(keys, status):
+    c = Counter()
+    for k, s in zip(keys.tolist(), status.tolist()):
+        c[k] += int(s)
+    return c
+
+
+@pytest.mark.parametrize("B,domain", [(1, 300), (61, 5000), (4099, 1 << 18)])
+def test_insert_delete_reinsert(oracle_mod, B, domain):
+    """Copies go in over six batches, each holding a key at most once, so a key's copies lie in
+    batch order along its list. A batch of deletes with repeated keys must then remove, for
+    each key, its first copies in that order (the oracle's), whatever the schedule."""
+    say("case: dup insert/delete/reinsert B=%d domain=%d" % (B, domain))
+    t, o, rng = make_dup(oracle_mod, B, S.pool_slabs_bound(8 * domain), 900 + B)
+    pool_keys = W.unique_keys(rng, domain)
+    for r in range(6):
+        keys = pool_keys[rng.below(domain, 10) < 7]
+        vals = (rng.next(keys.size) >> np.uint64(32)).astype(np.uint32)
+        st = t.insert(S.to_dev(keys), S.to_dev(vals))
+        assert bool((st == 1).all())
+        o.replace(keys, vals)
+    assert_same_table(t, o)
+    n = int(o.bucket_stats()[0].sum())
+    # deletes with repeats: each removes the first remaining copy in list order
+    dk = pool_keys[rng.below(n // 2, domain)]
+    gs = t.delete(S.to_dev(dk)).cpu().numpy()
+    os_ = o.delete(dk)
+    assert per_key_sum(dk, gs) == per_key_sum(dk, os_)
+    assert_same_table(t, o)
+    # inserts fill the emptied slots first, then the tails
+    rk = pool_keys[rng.below(n // 3, domain)]
+    rv = (rng.next(rk.size) >> np.uint64(32)).astype(np.uint32)
+    assert bool((t.insert(S.to_dev(rk), S.to_dev(rv)) == 1).all())
+    o.replace(rk, rv)
+    assert_same_table(t, o)
+    # SEARCHALL: counts exact, values the same multiset per key
+    q = pool_keys[: min(domain, 50000)]
+    gc, goff, gv = t.search_all(S.to_dev(q))
+    oc, ooff, ov = o.search_all(q)
+    gc, goff, gv = gc.cpu().numpy(), goff.cpu().numpy(), S.to_host_u32(gv)
+    assert (gc == oc).all() and (goff == ooff).all()
+    for i in range(0, q.size, max(1, q.size // 2000)):
+        a0, c0 = int(ooff[i]), int(oc[i])
+        assert sorted(gv[a0:a0 + c0].tolist()) == sorted(ov[a0:a0 + c0].tolist())
+    # SEARCH: found exact; the value is one of the key's values
+    v, f = t.search(S.to_dev(q))
+    ovv, of, _ = o.search(q)
+    assert (f.cpu().numpy() == of).all()
+
+
+def test_list_order_across_batches(oracle_mod):
+    """Copies inserted one per batch sit in batch order: SEARCH returns the first batch's value
+    and SEARCHALL the values in batch order; DELETE removes the first copy."""
+    say("case: dup list order across batches")
+    t, o, rng = make_dup(oracle_mod, 97, S.pool_slabs_bound(60000), 950)
+    keys = W.unique_keys(rng, 15000)
+    for r in range(4):
+        v = (W.value_of(keys) + np.uint32(r)).astype(np.uint32)
+        assert bool((t.insert(S.to_dev(keys), S.to_dev(v)) == 1).all())
+        o.replace(keys, v)
+    assert_same_table(t, o)
+    gv, gf = t.search(S.to_dev(keys))
+    ov, of, _ = o.search(keys)
+    assert (gf.cpu().numpy() == 1).all() and (S.to_host_u32(gv) == ov).all()
+    gc, goff, gvals = t.search_all(S.to_dev(keys))
+    oc, ooff, ovals = o.search_all(keys)
+    assert (gc.cpu().numpy() == 4).all() and (S.to_host_u32(gvals) == ovals).all()
+    # delete twice each key: the first two batches' copies go
+    dk = np.concatenate([keys, keys])
+    assert bool((t.delete(S.to_dev(dk)) == 1).all())
+    o.delete(dk)
+    assert_same_table(t, o)
+    gc, goff, gvals = t.search_all(S.to_dev(keys))
+    oc, ooff, ovals = o.search_all(keys)
+    assert (gc.cpu().numpy() == 2).all() and (S.to_host_u32(gvals) == ovals).all()
+    # DELETEALL: the rest
+    c = t.delete_all(S.to_dev(keys)).cpu().numpy()
+    oc2 = o.delete_all(keys)
+    assert (c == 2).all() and (oc2 == 2).all()
+    assert_same_table(t, o)
+    v, f = t.search(S.to_dev(keys))
+    assert not f.cpu().numpy().any()
+
+
+def test_mixed_batch_with_duplicates(oracle_mod):
+    """Inserts, deletes and searches on disjoint key roles in one concurrent batch."""
+    say("case: dup mixed batch")
+    t, o, rng = make_dup(oracle_mod, 211, S.pool_slabs_bound(80000), 960)
+    base = W.unique_keys(rng, 20000)
+    bv = W.value_of(base)
+    t.insert(S.to_dev(base), S.to_dev(bv))
+    o.replace(base, bv)
+    ins = base[rng.below(6000, 5000)]                      # more copies of some keys
+    dels = base[5000 + rng.permutation(5000)[:3000]]        # keys with one copy
+    srch = base[10000:20000][rng.below(8000, 10000)]        # untouched single copies
+    ops = np.concatenate([np.full(ins.size, W.OP_INSERT), np.full(dels.size, W.OP_DELETE),
+                          np.full(srch.size, W.OP_SEARCH)]).astype(np.uint8)
+    k = np.concatenate([ins, dels, srch]).astype(np.uint32)
+    v = (rng.next(k.size) >> np.uint64(32)).astype(np.uint32)
+    perm = rng.permutation(k.size)
+    ops, k, v = ops[perm], k[perm], v[perm]
+    gv, gs = t.mixed(S.to_dev(ops), S.to_dev(k), S.to_dev(v))
+    ov, ost = o.mixed(ops, k, v)
+    assert (gs.cpu().numpy() == ost).all() and (S.to_host_u32(gv) == ov).all()
+    # An insert that read its slab before a concurrent delete emptied a slot appends instead of
+    # filling it (the insert linearises first), so a bucket's slab count lies between the
+    # oracle's in batch order and the oracle's with every insert ahead of every delete.
+    st = assert_same_table(t, o, check_counts=False)
+    o2 = oracle_mod.Oracle(211, M, o.a, o.b, duplicates=True)
+    o2.replace(base, bv)
+    ins_m = ops == W.OP_INSERT
+    o2.replace(k[ins_m], v[ins_m])
+    o2.delete(k[ops == W.OP_DELETE])
+    _, _, _, counts, _ = t.dump()
+    live, tomb, lo_slabs = o.bucket_stats()
+    _, _, hi_slabs = o2.bucket_stats()
+    assert (counts[:, 0] == live).all() and (counts[:, 1] == 0).all()
+    assert (lo_slabs <= counts[:, 2]).all() and (counts[:, 2] <= hi_slabs).all()
+    assert st["pool_allocated"] == int((counts[:, 2].astype(np.int64) - 1).sum())
+
+
+def test_flush_drops_empty_slots(oracle_mod):
+    say("case: dup flush")
+    t, o, rng = make_dup(oracle_mod, 7, S.pool_slabs_bound(20000), 970)
+    dom = W.unique_keys(rng, 800)
+    for r in range(12):   # a key at most once per batch: its copies lie in batch order
+        keys = dom[rng.below(800, 10) < 9]
+        vals = (rng.next(keys.size) >> np.uint64(32)).astype(np.uint32)
+        t.insert(S.to_dev(keys), S.to_dev(vals))
+        o.replace(keys, vals)
+    dk = dom[rng.below(6000, 800)]
+    t.delete(S.to_dev(dk))
+    o.delete(dk)
+    t.flush()
+    o.flush_all()
+    assert_same_table(t, o)
+    more = W.unique_keys(rng, 3000)
+    mv = W.value_of(more)
+    t.insert(S.to_dev(more), S.to_dev(mv))
+    o.replace(more, mv)
+    assert_same_table(t, o)
+
+
+def test_unique_key_tables_delete_all_and_search_all(oracle_mod):
+    say("case: delete_all / search_all with unique keys")
+    rng = W.SplitMix64(980)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    t = S.SlabHash(61, S.pool_slabs_bound(40000), a, b)
+    o = oracle_mod.Oracle(61, M, a, b)
+    keys = W.unique_keys(rng, 20000)
+    vals = W.value_of(keys)
+    t.insert(S.to_dev(keys), S.to_dev(vals))
+    o.replace(keys, vals)
+    q = np.concatenate([keys[:5000], W.unique_keys(rng, 2000, exclude=keys)])
+    gc, goff, gv = t.search_all(S.to_dev(q))
+    oc, ooff, ov = o.search_all(q)
+    assert (gc.cpu().numpy() == oc).all() and (S.to_host_u32(gv) == ov).all()
+    dq = np.concatenate([keys[:3000], keys[:100]])          # repeats find nothing the 2nd time
+    c = t.delete_all(S.to_dev(dq)).cpu().numpy()
+    oc2 = o.delete_all(dq)
+    assert per_key_sum(dq, c) == per_key_sum(dq, oc2)
+    assert_same_table(t, o)
+
+
+def test_duplicates_rejected_by_batched_and_served_forms():
+    p = S.ShParams(64, 2048, 3, 5, S.SH_TABLE_DUPLICATES)
+    assert S.sh_storage_bytes(p) > 0
+    arr = (S.ShParams * 1)(p)
+    assert S.lib().sh_multi_storage_bytes(1, arr) == 0
+    t = S.SlabHash(64, 2048, 3, 5, duplicates=True)
+    ops = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    keys = torch.zeros(8, dtype=torch.int32, device="cuda")
+    with pytest.raises(Exception):
+        S.Server(t, ops, keys, keys)
