@@ -466,6 +466,64 @@ def sweep_batches(log2_batches=(15, 16, 17), total: int = 1 << 24, B: int = 7932
     return out
 
 
+def measure_duplicates(n_keys: int = 1 << 20, copies: int = 4, B: int = 217316,
+                       reps: int = 3) -> dict:
+    """The multiset operations ("Supported Operations") on a table with duplicates allowed: 2^20
+    keys, each inserted `copies` times (one copy per INSERT batch of 2^20), then SEARCH of 2^22
+    random copies' keys, SEARCHALL of every key (a counting pass, then a pass writing the values
+    into ranges sized from the counts), DELETE of each key's first copy and DELETEALL of the
+    rest. Median of `reps` runs on a rebuilt table, HIP events around each call."""
+    import torch
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    keys = W.distinct_keys(81, 0, n_keys)
+    kd = S.to_dev(keys)
+    vd = [S.to_dev((W.value_of(keys) + np.uint32(c)).astype(np.uint32)) for c in range(copies)]
+    q = S.to_dev(keys[W.SplitMix64(82).below(copies * n_keys, n_keys)])
+    rng = W.SplitMix64(83)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    t = S.SlabHash(B, S.pool_slabs_bound(copies * n_keys), a, b, duplicates=True)
+    st = torch.empty(n_keys, dtype=torch.uint8, device="cuda")
+    vo = torch.empty(q.numel(), dtype=torch.int32, device="cuda")
+    fo = torch.empty(q.numel(), dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(n_keys, dtype=torch.int32, device="cuda")
+    off = torch.arange(0, copies * n_keys, copies, dtype=torch.int64, device="cuda")
+    vals = torch.empty(copies * n_keys, dtype=torch.int32, device="cuda")
+    names = ["insert", "search", "search_all_count", "search_all_values", "delete",
+             "delete_all"]
+    res = {k: [] for k in names}
+    for _ in range(reps):
+        t.reset()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        e[0].record()
+        for c in range(copies):
+            S.sh_insert(t.handle, kd, vd[c], st)
+        e[1].record()
+        S.sh_search(t.handle, q, vo, fo)
+        e[2].record()
+        S.sh_search_all(t.handle, kd, cnt)
+        e[3].record()
+        S.sh_search_all(t.handle, kd, cnt, off, vals)
+        e[4].record()
+        S.sh_delete(t.handle, kd, st)
+        e[5].record()
+        S.sh_delete_all(t.handle, kd, cnt)
+        e[6].record()
+        torch.cuda.synchronize()
+        for i, k in enumerate(names):
+            res[k].append(e[i].elapsed_time(e[i + 1]))
+    assert bool((cnt == copies - 1).all()) and bool((st == 1).all())
+    units = {"insert": copies * n_keys, "search": q.numel(), "search_all_count": n_keys,
+             "search_all_values": n_keys, "delete": n_keys, "delete_all": n_keys}
+    out = {"workload": "duplicates allowed: 2^20 keys x %d copies (one copy per insert batch), "
+                       "B=%d" % (copies, B)}
+    for k in names:
+        ms = float(np.median(res[k]))
+        out[k + "_ms"] = round(ms, 4)
+        out[k + "_Mops"] = round(units[k] / (ms * 1e-3) / 1e6, 1)
+    return out
+
+
 def measure_flush(table, keys, vals, st, stream, reps: int = 5) -> dict:
     """FLUSH of every bucket ("Flush" subsection) of the benchmark table after half of its 2^22
     keys have been deleted: median of `reps` runs, each on a freshly built and half-deleted
@@ -722,6 +780,9 @@ def main():
     log("allocator")
     allocator = measure_alloc()
 
+    log("duplicates")
+    duplicates = measure_duplicates()
+
     log("access-pattern ceilings")
     patterns = measure_patterns(int(table.storage.numel()), N_KEYS)
     # each kernel against the ceiling of its own access pattern, measured above
@@ -835,6 +896,7 @@ def main():
         "access_patterns": patterns,
         "flush": flush,
         "allocator": allocator,
+        "duplicates": duplicates,
         "cpu_baseline": cpu,
     }
     if sweep is not None:

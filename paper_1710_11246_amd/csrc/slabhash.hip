@@ -341,9 +341,11 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
             }
             bool target;
             uint32_t code;
+            uint32_t empties = 0;
             if constexpr (kHasIns) {
                 const bool is_empty = !is31 && w == kEmptyPair;
                 const uint32_t eh = (uint32_t)(ballot(is_empty) >> hshift);
+                empties = eh;
                 const bool first_empty = ins && is_empty && (eh & below) == 0u;
                 const bool tail = is31 && (!ins || eh == 0u);
                 // with duplicates an insert takes the first empty slot whatever keys it meets
@@ -358,8 +360,11 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
                 target = is_key || (kh == 0u && is31);
                 code = is_key ? code_key : (hi != kEmpty ? kMsgMove : kMsgEnd);
             }
+            // an insert into an empty slot carries, with duplicates, the slab's other empty
+            // slots (empty slots need not be a suffix there) in place of the value
+            const uint32_t payload = (Dup && code == kMsgSwapIns) ? empties : hi;
             if (target)
-                L.msg[2 * q + half] = ((uint64_t)((code << 8) | slot) << 32) | hi;
+                L.msg[2 * q + half] = ((uint64_t)((code << 8) | slot) << 32) | payload;
         }
         __builtin_amdgcn_wave_barrier();
         // ---- 3. act on the outcome ----
@@ -391,7 +396,20 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
                 if (old == expect) {
                     rs = (code == kMsgSwapRep) ? 2u : 1u;
                     won = true;
-                } else if (code == kMsgSwapIns && !Dup) {
+                } else if (code == kMsgSwapIns && Dup) {
+                    // try the empty slots after the lost one that the slab read showed
+                    uint32_t m = payload & ~((2u << cslot) - 1u);
+                    while (m) {
+                        cslot = (uint32_t)__builtin_ctz(m);
+                        m &= m - 1u;
+                        if (cas64(slab + cslot, kEmptyPair, desired) == kEmptyPair) {
+                            rs = 1u;
+                            won = true;
+                            break;
+                        }
+                    }
+                    lost = !won; // all taken: the next round re-reads the slab
+                } else if (code == kMsgSwapIns) {
                     // Walk forward from the lost empty slot using the occupants the swaps
                     // return; at most the 31 slots of this slab. (With duplicates, empty slots
                     // need not be a suffix, so a lost insert re-reads its slab next round.)
