@@ -65,15 +65,20 @@ enum { SH_ERR_RESERVED_KEY = 1u, SH_ERR_POOL_EXHAUSTED = 2u };
    insert adds its pair without looking for the key (INSERT, not REPLACE), and a delete turns the
    first matching slot into an empty slot that later inserts may fill (the paper's deletion when
    duplicates are allowed). Without it keys are unique (REPLACE) and deleted slots stay
-   tombstones. Searches return the first match in list order in both modes. */
-enum { SH_TABLE_DUPLICATES = 1u };
+   tombstones. Searches return the first match in list order in both modes.
+   With SH_TABLE_KEYS_ONLY the table holds keys alone (the paper's 32-bit entries): a slab holds
+   62 keys, then its auxiliary word and next index, each four bytes. Inserts ignore d_vals (it may
+   be NULL); a search that finds its key reports the key itself as the value. 0xFFFFFFFE is then
+   reserved too, as the deleted-entry marker (the paper reserves two key values, empty and
+   deleted); an operation carrying it fails like one carrying 0xFFFFFFFF. The two flags combine. */
+enum { SH_TABLE_DUPLICATES = 1u, SH_TABLE_KEYS_ONLY = 2u };
 
 typedef struct {
     uint32_t num_buckets; /* B >= 1 */
     uint32_t pool_slabs;  /* slabs beyond the base slabs; a multiple of SH_BLOCK_SLABS, may be 0 */
     uint32_t hash_a;      /* 1 <= a < p */
     uint32_t hash_b;      /* 0 <= b < p */
-    uint32_t flags;       /* 0 or SH_TABLE_DUPLICATES; other bits are invalid */
+    uint32_t flags;       /* SH_TABLE_DUPLICATES and/or SH_TABLE_KEYS_ONLY; other bits invalid */
 } sh_params_t;
 
 /* Launch shape of the operation kernels. Never changes results.
@@ -247,7 +252,7 @@ size_t sh_multi_storage_bytes(uint32_t T, const sh_params_t *h_params);
 
 /* Bind T tables to caller-owned storage (256-byte aligned, at least sh_multi_storage_bytes) and
    enqueue their initialisation and the directory upload on `stream`. The batched kernel runs
-   the unique-key operations: tables with SH_TABLE_DUPLICATES give SH_EINVAL. */
+   the unique-key operations on key-value pairs: tables with any flag give SH_EINVAL. */
 sh_status_t sh_multi_create(uint32_t T, const sh_params_t *h_params, void *d_storage,
                             size_t bytes, void *stream, sh_multi_t **out);
 
@@ -328,8 +333,8 @@ size_t sh_server_scratch_bytes(const sh_server_cfg_t *cfg);
 
 /* Start serving table t. d_scratch: caller-owned device memory (256-byte aligned, at least
    sh_server_scratch_bytes). Synchronises `stream` once to read the pool occupancy. No other call
-   may use the table while the server runs. A table with SH_TABLE_DUPLICATES gives SH_EINVAL
-   (requests run through the batched kernel). */
+   may use the table while the server runs. A table with any flag gives SH_EINVAL (requests run
+   through the batched kernel). */
 sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uint8_t *d_ops,
                             const uint32_t *d_keys, const uint32_t *d_vals_in,
                             uint32_t *d_vals_out, uint8_t *d_status, uint64_t n_ops,

@@ -38,6 +38,8 @@ namespace {
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint64_t kEmptyPair = ~0ull;
 constexpr uint64_t kTombPair = 0x00000000FFFFFFFFull; // key half all ones, value half 0
+constexpr uint32_t kTombKey = 0xFFFFFFFEu;            // a deleted entry of a key-only slab
+constexpr uint32_t kKeyEntries = 62;                  // keys per key-only slab
 constexpr uint64_t kSlotMask = 0x7FFFFFFFull;         // slots 0..30 of a half wavefront
 constexpr uint32_t kPrime = SH_HASH_PRIME;
 constexpr int kBlock = 256;
@@ -63,7 +65,7 @@ struct View {
     Header *hdr;
     unsigned long long *counters; // kCounterSlots x 8
     uint32_t B, a, b, pool_slabs, nblk;
-    uint32_t dup; // 1 = duplicates allowed (SH_TABLE_DUPLICATES)
+    uint32_t mode; // SH_TABLE_DUPLICATES | SH_TABLE_KEYS_ONLY bits of the table's flags
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -270,7 +272,7 @@ struct WaveLds {
 
 // One chunk of up to 64 ops (lane l < count holds op base + l) on table T, processed in rounds
 // until every op has finished (see the description above).
-template <int K, bool Dup>
+template <int K, bool Dup, bool KO>
 __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
                           const uint8_t *__restrict__ ops, const uint32_t *__restrict__ keys,
                           const uint32_t *__restrict__ vals, uint32_t *__restrict__ vout,
@@ -289,12 +291,13 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
     const bool in = lane < count;
     const uint32_t key = in ? keys[i] : kEmpty;
     uint32_t val = 0;
-    if constexpr (kHasIns)
+    if constexpr (kHasIns && !KO)
         val = in ? vals[i] : 0;
     uint32_t op = (uint32_t)K;
     if constexpr (K == kMixed)
         op = in ? (uint32_t)ops[i] : 0u;
-    const bool reserved = in && key == kEmpty;
+    // key-only slabs reserve a second key, the deleted-entry marker
+    const bool reserved = in && (key == kEmpty || (KO && key == kTombKey));
     const uint64_t res_m = ballot(reserved);
     if (res_m)
         raise_error(T, SH_ERR_RESERVED_KEY, lane, ffs0(res_m));
@@ -326,10 +329,15 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
             const uint64_t w = pre[q];
             const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
             const uint32_t kq = L.key[2 * q + half];
-            const bool match = !is31 && lo == kq;
+            // a key-value slab holds one pair per lane (key in lo); a key-only slab two keys per
+            // lane, entries 2 slot (lo) and 2 slot + 1 (hi)
+            const bool mlo = !is31 && lo == kq;
+            const bool mhi = KO && !is31 && hi == kq;
+            const bool match = mlo || mhi;
             const uint32_t kh = (uint32_t)(ballot(match) >> hshift); // my half's key votes
             // the op's slot is the first match of the slab (with unique keys the only one)
             const bool is_key = Dup ? (match && (kh & below) == 0u) : match;
+            const uint32_t kslot = KO ? (mlo ? 2 * slot : 2 * slot + 1) : slot;
             bool ins = (K == kInsert);
             uint32_t code_key = (K == kSearch) ? kMsgFound
                                                : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
@@ -340,10 +348,12 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
                                            : ((oq == kDelete) ? kMsgSwapDel : kMsgSwapRep);
             }
             bool target;
-            uint32_t code;
+            uint32_t code, tslot = slot;
             uint32_t empties = 0;
             if constexpr (kHasIns) {
-                const bool is_empty = !is31 && w == kEmptyPair;
+                const bool elo = !is31 && (KO ? lo == kEmpty : w == kEmptyPair);
+                const bool ehi = KO && !is31 && hi == kEmpty;
+                const bool is_empty = elo || ehi;
                 const uint32_t eh = (uint32_t)(ballot(is_empty) >> hshift);
                 empties = eh;
                 const bool first_empty = ins && is_empty && (eh & below) == 0u;
@@ -356,15 +366,23 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
                            : (first_empty ? kMsgSwapIns
                                           : (hi != kEmpty ? kMsgMove
                                                           : (ins ? kMsgGrow : kMsgEnd)));
+                if (hit)
+                    tslot = kslot;
+                else if (first_empty)
+                    tslot = KO ? (elo ? 2 * slot : 2 * slot + 1) : slot;
             } else {
                 target = is_key || (kh == 0u && is31);
                 code = is_key ? code_key : (hi != kEmpty ? kMsgMove : kMsgEnd);
+                if (is_key)
+                    tslot = kslot;
             }
-            // an insert into an empty slot carries, with duplicates, the slab's other empty
-            // slots (empty slots need not be a suffix there) in place of the value
-            const uint32_t payload = (Dup && code == kMsgSwapIns) ? empties : hi;
+            // the payload: the value found (in a key-only slab, the key itself), the next index,
+            // or for an insert into an empty slot with duplicates, the lanes of the slab that
+            // showed an empty slot (empty slots need not be a suffix there)
+            const uint32_t payload =
+                (Dup && code == kMsgSwapIns) ? empties : ((KO && is_key) ? kq : hi);
             if (target)
-                L.msg[2 * q + half] = ((uint64_t)((code << 8) | slot) << 32) | payload;
+                L.msg[2 * q + half] = ((uint64_t)((code << 8) | tslot) << 32) | payload;
         }
         __builtin_amdgcn_wave_barrier();
         // ---- 3. act on the outcome ----
@@ -383,7 +401,62 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
         uint64_t alloc_m = 0;
         if constexpr (K != kSearch) {
             bool won = false, lost = false;
-            if (code >= kMsgSwapIns) {
+            if (KO && code >= kMsgSwapIns) {
+                // key-only slab: 32-bit swaps on single entries
+                uint32_t *ent = reinterpret_cast<uint32_t *>(
+                    T.base + (size_t)((loc == kEmpty) ? bkt : T.B + loc) * 32);
+                uint32_t e = tslot;
+                if (code == kMsgSwapRep) {
+                    rs = 2u; // the key is already there: nothing to replace
+                    won = true;
+                } else if (code == kMsgSwapDel) {
+                    won = cas32(ent + e, key, Dup ? kEmpty : kTombKey) == key;
+                    rs = won ? 1u : 0u;
+                    lost = !won;
+                } else {
+                    uint32_t old = cas32(ent + e, kEmpty, key);
+                    if (old == kEmpty) {
+                        rs = 1u;
+                        won = true;
+                    } else if (!Dup) {
+                        // entries fill in order: walk on with the occupants the swaps return
+                        for (;;) {
+                            if (old == key) {
+                                rs = 2u; // inserted meanwhile by another op
+                                won = true;
+                                break;
+                            }
+                            if (++e >= kKeyEntries) {
+                                lost = true;
+                                break;
+                            }
+                            old = cas32(ent + e, kEmpty, key);
+                            if (old == kEmpty) {
+                                rs = 1u;
+                                won = true;
+                                break;
+                            }
+                        }
+                    } else {
+                        // the rest of this lane, then the lanes that showed an empty entry
+                        if (!(e & 1u) && cas32(ent + e + 1, kEmpty, key) == kEmpty) {
+                            rs = 1u;
+                            won = true;
+                        }
+                        uint32_t m = payload & ~((2u << (e >> 1)) - 1u);
+                        while (!won && m) {
+                            const uint32_t l = (uint32_t)__builtin_ctz(m);
+                            m &= m - 1u;
+                            if (cas32(ent + 2 * l, kEmpty, key) == kEmpty ||
+                                cas32(ent + 2 * l + 1, kEmpty, key) == kEmpty) {
+                                rs = 1u;
+                                won = true;
+                            }
+                        }
+                        lost = !won;
+                    }
+                }
+            } else if (code >= kMsgSwapIns) {
                 uint32_t cslot = tslot;
                 uint64_t *slab = T.base + (size_t)((loc == kEmpty) ? bkt : T.B + loc) * 32;
                 // a delete leaves a tombstone, or with duplicates an empty slot
@@ -512,7 +585,7 @@ __device__ __forceinline__ void alloc_init(Alloc &al, uint32_t wave, uint32_t se
     al.rot = mix32(al.start) & 63u;
 }
 
-template <int K, bool Dup>
+template <int K, bool Dup, bool KO>
 __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__restrict__ ops,
                                                      const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ vals,
@@ -531,7 +604,8 @@ __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__re
     for (uint64_t c = wave; c < nchunks; c += nwaves) {
         const uint64_t base = c * C;
         const uint32_t count = (uint32_t)((n - base < C) ? n - base : C);
-        run_chunk<K, Dup>(T, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base, count, flags);
+        run_chunk<K, Dup, KO>(T, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base, count,
+                              flags);
     }
     if (flags & kFlagCounters)
         flush_counters(T, cnt, al, wave);
@@ -619,8 +693,8 @@ __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ 
             count = 0; // range outside the op arrays: nothing is read or written
         else if (count > n_ops - base)
             count = n_ops - base;
-        run_chunk<kMixed, false>(Tv, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base,
-                                 (uint32_t)count, flags);
+        run_chunk<kMixed, false, false>(Tv, al, cnt, lds[wl_], ops, keys, vals, vout, sout,
+                                        base, (uint32_t)count, flags);
     }
     if ((flags & kFlagCounters) && cur_t != kEmpty)
         flush_counters(dir[cur_t], cnt, al, wave);
@@ -636,11 +710,13 @@ __device__ __forceinline__ bool bitmap_has(const View &T, uint32_t idx)
     return (w >> (idx & 31)) & 1u;
 }
 
+template <bool KO>
 __global__ __launch_bounds__(kBlock) void walk_kernel(View T, uint32_t *__restrict__ dbkt,
                                                       uint32_t *__restrict__ dkey,
                                                       uint32_t *__restrict__ dval, uint64_t cap,
                                                       uint32_t *__restrict__ counts, int emit)
 {
+    const bool dup = (T.mode & SH_TABLE_DUPLICATES) != 0;
     const uint32_t lane = lane_id();
     const uint32_t slot = lane & 31;
     const uint32_t wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -654,20 +730,70 @@ __global__ __launch_bounds__(kBlock) void walk_kernel(View T, uint32_t *__restri
             const uint64_t w = cur[slot];
             const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
             ++ns;
-            const uint64_t E = ballot(w == kEmptyPair) & kSlotMask;
-            const uint64_t L = ballot(lo != kEmpty) & kSlotMask;
-            const uint64_t Tm = ballot(w == kTombPair) & kSlotMask;
-            const uint64_t bad = ballot(lo == kEmpty && hi != kEmpty && hi != 0u) & kSlotMask;
-            nl += __popcll(L);
-            nt += __popcll(Tm);
-            if (bad)
-                ++viol;
-            if (!T.dup && E && E != (kSlotMask & ~((1ull << ffs0(E)) - 1)))
-                ++viol; // empty slots must form a suffix (with unique keys)
+            uint64_t E, L;
+            if constexpr (KO) {
+                // two entries per lane (2 slot in lo, 2 slot + 1 in hi); lane 31: aux and next
+                const bool s31 = slot == 31;
+                const bool elo = !s31 && lo == kEmpty, ehi = !s31 && hi == kEmpty;
+                const uint64_t Llo = ballot(!s31 && lo != kEmpty && lo != kTombKey) & kSlotMask;
+                const uint64_t Lhi = ballot(!s31 && hi != kEmpty && hi != kTombKey) & kSlotMask;
+                nl += __popcll(Llo) + __popcll(Lhi);
+                nt += __popcll(ballot(!s31 && lo == kTombKey) & kSlotMask) +
+                      __popcll(ballot(!s31 && hi == kTombKey) & kSlotMask);
+                const uint64_t Eall = ballot(elo && ehi) & kSlotMask;
+                const uint64_t Ehi = ballot(!elo && ehi) & kSlotMask;
+                const uint64_t Ebad = ballot(elo && !ehi) & kSlotMask;
+                E = Eall | Ehi | Ebad;
+                L = Llo | Lhi;
+                if (!dup) {
+                    // empty entries form a suffix: full lanes, at most one lane with only its
+                    // high entry empty, then empty lanes
+                    const uint64_t full = kSlotMask & ~E;
+                    const uint32_t nf = (uint32_t)__popcll(full);
+                    if (Ebad || full != (1ull << nf) - 1 || (Ehi && Ehi != (1ull << nf)))
+                        ++viol;
+                }
+                if (emit && L) {
+                    unsigned long long pos0 = 0;
+                    const uint32_t ne = (uint32_t)(__popcll(Llo) + __popcll(Lhi));
+                    if (lane == 0)
+                        pos0 = atomicAdd(&T.hdr->dump_count, (unsigned long long)ne);
+                    pos0 = ((unsigned long long)rl((uint32_t)(pos0 >> 32), 0) << 32) |
+                           rl((uint32_t)pos0, 0);
+                    if (lane < 32) {
+                        const uint64_t lb = (1ull << lane) - 1;
+                        const bool ilo = (Llo >> lane) & 1, ihi = (Lhi >> lane) & 1;
+                        const uint64_t p =
+                            pos0 + __popcll(Llo & lb) + __popcll(Lhi & lb);
+                        if (ilo && p < cap) {
+                            dbkt[p] = b;
+                            dkey[p] = lo;
+                            dval[p] = lo;
+                        }
+                        if (ihi && p + ilo < cap) {
+                            dbkt[p + ilo] = b;
+                            dkey[p + ilo] = hi;
+                            dval[p + ilo] = hi;
+                        }
+                    }
+                }
+            } else {
+                E = ballot(w == kEmptyPair) & kSlotMask;
+                L = ballot(lo != kEmpty) & kSlotMask;
+                const uint64_t Tm = ballot(w == kTombPair) & kSlotMask;
+                const uint64_t bad =
+                    ballot(lo == kEmpty && hi != kEmpty && hi != 0u) & kSlotMask;
+                nl += __popcll(L);
+                nt += __popcll(Tm);
+                if (bad)
+                    ++viol;
+                if (!dup && E && E != (kSlotMask & ~((1ull << ffs0(E)) - 1)))
+                    ++viol; // empty slots must form a suffix (with unique keys)
+            }
             const uint32_t aux = rl(lo, 31), next = rl(hi, 31);
             if (aux != kEmpty)
                 ++viol;
-            if (emit && L) {
+            if (!KO && emit && L) {
                 unsigned long long pos0 = 0;
                 if (lane == 0)
                     pos0 = atomicAdd(&T.hdr->dump_count, (unsigned long long)__popcll(L));
@@ -684,7 +810,7 @@ __global__ __launch_bounds__(kBlock) void walk_kernel(View T, uint32_t *__restri
             }
             if (next == kEmpty)
                 break;
-            if (E && !T.dup)
+            if (E && !dup)
                 ++viol; // a slab with a successor must be full (with unique keys)
             if (next >= T.pool_slabs || !bitmap_has(T, next) || ns > T.pool_slabs) {
                 ++viol;
@@ -721,8 +847,11 @@ __global__ __launch_bounds__(kBlock) void walk_kernel(View T, uint32_t *__restri
 // of its own: no operation touches the table while it runs. A next index outside the pool (a
 // well-formed table has none; the structure walk of sh_stats reports one) leaves the rest of
 // that bucket as it is.
+template <bool KO>
 __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, uint32_t count)
 {
+    // slots per slab: 31 pairs, or 62 keys of a key-only slab (entries 2 slot and 2 slot + 1)
+    constexpr uint32_t kCap = KO ? kKeyEntries : 31u;
     const uint32_t lane = lane_id();
     const uint32_t slot = lane & 31;
     const uint32_t below = (1u << slot) - 1u;
@@ -731,34 +860,49 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
     for (uint32_t i = wave; i < count; i += nwaves) {
         const uint32_t bkt = first + i;
         uint32_t ru = bkt;         // unified index of the slab being read
-        uint32_t wu = bkt, ws = 0; // write position: slot ws of slab wu (31 = wu is full)
+        uint32_t wu = bkt, ws = 0; // write position: slot ws of slab wu (kCap = wu is full)
         uint32_t seen = 0, nxt = kEmpty;
         uint64_t w = 0;
         bool ok = true;
         for (;;) {
             w = T.base[(size_t)ru * 32 + slot];
             nxt = rl((uint32_t)(w >> 32), 31);
-            const bool live = slot < 31 && (uint32_t)w != kEmpty;
+            const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+            const bool live = slot < 31 && lo != kEmpty && (!KO || lo != kTombKey);
+            const bool live_hi = KO && slot < 31 && hi != kEmpty && hi != kTombKey;
             const uint32_t lm = (uint32_t)ballot(live); // lanes 0..31; 32..63 mirror them
-            const uint32_t cnt = (uint32_t)__popc(lm);
+            const uint32_t hm = (uint32_t)ballot(live_hi);
+            const uint32_t cnt = (uint32_t)(__popc(lm) + __popc(hm));
             if (cnt) {
-                // pairs past slot 30 of wu go to the slab after it, which the walk has passed
+                // entries past the last slot of wu go to the slab after it, which the walk has
+                // passed
                 uint32_t spill = 0;
-                if (ws + cnt > 31) {
+                if (ws + cnt > kCap) {
                     spill = (uint32_t)(T.base[(size_t)wu * 32 + 31] >> 32);
                     if (spill >= T.pool_slabs) {
                         ok = false;
                         break;
                     }
                 }
-                const uint32_t pos = ws + (uint32_t)__popc(lm & below);
-                const uint32_t du = (pos < 31) ? wu : T.B + spill;
-                const uint32_t ds = (pos < 31) ? pos : pos - 31;
-                if (lane < 32 && live && (du != ru || ds != slot)) // pairs already in place stay
-                    T.base[(size_t)du * 32 + ds] = w;
-                if (ws + cnt > 31) {
+                const uint32_t pos = ws + (uint32_t)(__popc(lm & below) + __popc(hm & below));
+                const uint32_t du = (pos < kCap) ? wu : T.B + spill;
+                const uint32_t ds = (pos < kCap) ? pos : pos - kCap;
+                if constexpr (KO) {
+                    uint32_t *ent = reinterpret_cast<uint32_t *>(T.base);
+                    const uint32_t pos2 = pos + (live ? 1u : 0u); // the high entry's position
+                    const uint32_t du2 = (pos2 < kCap) ? wu : T.B + spill;
+                    const uint32_t ds2 = (pos2 < kCap) ? pos2 : pos2 - kCap;
+                    if (lane < 32 && live && (du != ru || ds != 2 * slot)) // entries in place stay
+                        ent[(size_t)du * 64 + ds] = lo;
+                    if (lane < 32 && live_hi && (du2 != ru || ds2 != 2 * slot + 1))
+                        ent[(size_t)du2 * 64 + ds2] = hi;
+                } else {
+                    if (lane < 32 && live && (du != ru || ds != slot)) // pairs in place stay
+                        T.base[(size_t)du * 32 + ds] = w;
+                }
+                if (ws + cnt > kCap) {
                     wu = T.B + spill;
-                    ws = ws + cnt - 31;
+                    ws = ws + cnt - kCap;
                 } else {
                     ws += cnt;
                 }
@@ -780,9 +924,18 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
         if (wu != ru)
             rest = rl((uint32_t)(T.base[(size_t)wu * 32 + slot] >> 32), 31);
         // the last slab read still holds its own words in w; an earlier tail is rewritten whole
-        const bool keep = wu == ru && w == kEmptyPair;
-        if (lane < 32 && slot >= ws && !keep)
-            T.base[(size_t)wu * 32 + slot] = kEmptyPair;
+        if constexpr (KO) {
+            uint32_t *ent = reinterpret_cast<uint32_t *>(T.base) + (size_t)wu * 64;
+            const bool same = wu == ru;
+            if (lane < 32 && 2 * slot >= ws && !(same && (uint32_t)w == kEmpty))
+                ent[2 * slot] = kEmpty;
+            if (lane < 32 && 2 * slot + 1 >= ws && !(same && (uint32_t)(w >> 32) == kEmpty))
+                ent[2 * slot + 1] = kEmpty;
+        } else {
+            const bool keep = wu == ru && w == kEmptyPair;
+            if (lane < 32 && slot >= ws && !keep)
+                T.base[(size_t)wu * 32 + slot] = kEmptyPair;
+        }
         // the slabs that followed the tail go back to the pool, emptied
         uint32_t f = rest;
         seen = 0;
@@ -808,7 +961,7 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
 // DELETEALL swaps each matching slot to `gone` (a tombstone, or an empty slot with duplicates),
 // retrying a slot whose value a concurrent replace changed. counts[op] receives the number of
 // matches found (SEARCHALL) or deleted (DELETEALL).
-template <bool Del>
+template <bool Del, bool KO>
 __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__restrict__ keys,
                                                      uint64_t n, uint32_t *__restrict__ counts,
                                                      const uint64_t *__restrict__ offsets,
@@ -829,11 +982,13 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
         const uint32_t count = (n - base < 64) ? (uint32_t)(n - base) : 64u;
         const bool in = lane < count;
         const uint32_t key = in ? keys[base + lane] : kEmpty;
-        const uint64_t res_m = ballot(in && key == kEmpty);
+        const uint64_t res_m = ballot(in && (key == kEmpty || (KO && key == kTombKey)));
         if (res_m)
             raise_error(T, SH_ERR_RESERVED_KEY, lane, ffs0(res_m));
         kk[lane] = key;
-        uu[lane] = (in && key != kEmpty) ? bucket_of(key, T.a, T.b, T.B) : 0u;
+        uu[lane] = (in && key != kEmpty && !(KO && key == kTombKey))
+                       ? bucket_of(key, T.a, T.b, T.B)
+                       : 0u;
         __builtin_amdgcn_wave_barrier();
         uint64_t pre[32];
 #pragma unroll
@@ -845,7 +1000,7 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
                 break;
             const uint32_t op = 2 * q + half;
             const uint32_t kq = kk[op];
-            bool go = op < count && kq != kEmpty;
+            bool go = op < count && kq != kEmpty && !(KO && kq == kTombKey);
             uint64_t lim = 0, out0 = 0;
             if (!Del && vout && go) {
                 out0 = offsets[base + op];
@@ -855,11 +1010,21 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
             uint32_t u = uu[op], found = 0, steps = 0;
             for (;;) {
                 const bool m = go && slot < 31 && (uint32_t)w == kq;
+                const bool m2 = KO && go && slot < 31 && (uint32_t)(w >> 32) == kq;
                 const uint32_t mm = (uint32_t)(ballot(m) >> (lane & 32u));
-                uint32_t hits = (uint32_t)__popc(mm);
+                const uint32_t mm2 = (uint32_t)(ballot(m2) >> (lane & 32u));
+                uint32_t hits = (uint32_t)(__popc(mm) + __popc(mm2));
                 if constexpr (Del) {
-                    bool ok = false;
-                    if (m) {
+                    bool ok = false, ok2 = false;
+                    if constexpr (KO) {
+                        // key-only entries: the key is the whole entry, so one swap decides
+                        uint32_t *e = reinterpret_cast<uint32_t *>(T.base + (size_t)u * 32) +
+                                      2 * slot;
+                        if (m)
+                            ok = cas32(e, kq, (uint32_t)gone) == kq;
+                        if (m2)
+                            ok2 = cas32(e + 1, kq, (uint32_t)gone) == kq;
+                    } else if (m) {
                         uint64_t *p = T.base + (size_t)u * 32 + slot;
                         uint64_t expect = w;
                         for (;;) {
@@ -873,12 +1038,18 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
                             expect = old; // a replace changed the value: delete that
                         }
                     }
-                    hits = (uint32_t)__popc((uint32_t)(ballot(ok) >> (lane & 32u)));
+                    hits = (uint32_t)(__popc((uint32_t)(ballot(ok) >> (lane & 32u))) +
+                                      __popc((uint32_t)(ballot(ok2) >> (lane & 32u))));
                 } else {
-                    if (m && vout) {
-                        const uint64_t at = out0 + found + (uint32_t)__popc(mm & below);
-                        if (at < lim && at < vcap)
-                            vout[at] = (uint32_t)(w >> 32);
+                    if ((m || m2) && vout) {
+                        // in list order: entry 2 slot before 2 slot + 1, lanes in order
+                        const uint64_t at = out0 + found + (uint32_t)__popc(mm & below) +
+                                            (uint32_t)__popc(mm2 & below);
+                        if (m && at < lim && at < vcap)
+                            vout[at] = KO ? kq : (uint32_t)(w >> 32);
+                        const uint64_t at2 = at + (m ? 1u : 0u);
+                        if (m2 && at2 < lim && at2 < vcap)
+                            vout[at2] = kq;
                     }
                 }
                 found += hits;
@@ -1031,7 +1202,7 @@ bool layout_of(const sh_params_t *p, Layout *L)
     if (!p || p->num_buckets == 0 || p->pool_slabs % SH_BLOCK_SLABS != 0 || p->hash_a == 0 ||
         p->hash_a >= kPrime || p->hash_b >= kPrime ||
         (uint64_t)p->num_buckets + p->pool_slabs >= 0xFFFFFFFFull ||
-        (p->flags & ~(uint32_t)SH_TABLE_DUPLICATES) != 0)
+        (p->flags & ~(uint32_t)(SH_TABLE_DUPLICATES | SH_TABLE_KEYS_ONLY)) != 0)
         return false;
     L->base = kHeaderBytes;
     L->pool = L->base + (size_t)p->num_buckets * SH_SLAB_BYTES;
@@ -1100,14 +1271,26 @@ sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
     if (n >= (1ull << 32) || !keys)
         return SH_EINVAL;
     const uint32_t C = ops_per_wave_for(t, n);
-    if (t->v.dup)
-        hipLaunchKernelGGL((ops_kernel<K, true>), dim3(grid_for(t, n, C)), dim3(kBlock), 0,
-                           S(stream), t->v, ops, keys, vals, n, vout, sout, t->seq++, C,
-                           t->flags);
-    else
-        hipLaunchKernelGGL((ops_kernel<K, false>), dim3(grid_for(t, n, C)), dim3(kBlock), 0,
-                           S(stream), t->v, ops, keys, vals, n, vout, sout, t->seq++, C,
-                           t->flags);
+    const dim3 grid(grid_for(t, n, C));
+    const uint32_t seq = t->seq++;
+    switch (t->v.mode) {
+    case 0:
+        hipLaunchKernelGGL((ops_kernel<K, false, false>), grid, dim3(kBlock), 0, S(stream), t->v,
+                           ops, keys, vals, n, vout, sout, seq, C, t->flags);
+        break;
+    case SH_TABLE_DUPLICATES:
+        hipLaunchKernelGGL((ops_kernel<K, true, false>), grid, dim3(kBlock), 0, S(stream), t->v,
+                           ops, keys, vals, n, vout, sout, seq, C, t->flags);
+        break;
+    case SH_TABLE_KEYS_ONLY:
+        hipLaunchKernelGGL((ops_kernel<K, false, true>), grid, dim3(kBlock), 0, S(stream), t->v,
+                           ops, keys, vals, n, vout, sout, seq, C, t->flags);
+        break;
+    default:
+        hipLaunchKernelGGL((ops_kernel<K, true, true>), grid, dim3(kBlock), 0, S(stream), t->v,
+                           ops, keys, vals, n, vout, sout, seq, C, t->flags);
+        break;
+    }
     return check_launch();
 }
 
@@ -1122,8 +1305,12 @@ sh_status_t walk(sh_table *t, uint32_t *dbkt, uint32_t *dkey, uint32_t *dval, ui
     if (waves > t->p.num_buckets)
         waves = t->p.num_buckets;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(walk_kernel, dim3(blocks), dim3(kBlock), 0, S(stream), t->v, dbkt, dkey,
-                       dval, cap, counts, emit);
+    if (t->v.mode & SH_TABLE_KEYS_ONLY)
+        hipLaunchKernelGGL(walk_kernel<true>, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
+                           dbkt, dkey, dval, cap, counts, emit);
+    else
+        hipLaunchKernelGGL(walk_kernel<false>, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
+                           dbkt, dkey, dval, cap, counts, emit);
     if (check_launch() != SH_OK)
         return SH_EHIP;
     if (t->v.nblk) {
@@ -1177,7 +1364,7 @@ void bind_table(sh_table *t, const sh_params_t *p, char *storage, size_t bytes, 
     t->v.b = p->hash_b;
     t->v.pool_slabs = p->pool_slabs;
     t->v.nblk = p->pool_slabs / SH_BLOCK_SLABS;
-    t->v.dup = (p->flags & SH_TABLE_DUPLICATES) ? 1u : 0u;
+    t->v.mode = p->flags & (SH_TABLE_DUPLICATES | SH_TABLE_KEYS_ONLY);
 }
 
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1191,8 +1378,8 @@ size_t multi_layout(uint32_t T, const sh_params_t *p, size_t *offs)
     size_t off = round256((size_t)T * sizeof(View));
     for (uint32_t t = 0; t < T; ++t) {
         Layout L;
-        if (!layout_of(&p[t], &L) || (p[t].flags & SH_TABLE_DUPLICATES))
-            return 0; // the batched kernel runs the unique-key operations only
+        if (!layout_of(&p[t], &L) || p[t].flags != 0)
+            return 0; // the batched kernel runs the unique-key operations on pairs only
         if (offs)
             offs[t] = off;
         off += round256(L.total);
@@ -1289,8 +1476,12 @@ sh_status_t sh_flush(sh_table_t *t, uint32_t first_bucket, uint32_t num_buckets,
     if (waves > num_buckets)
         waves = num_buckets;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(flush_kernel, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
-                       first_bucket, num_buckets);
+    if (t->v.mode & SH_TABLE_KEYS_ONLY)
+        hipLaunchKernelGGL(flush_kernel<true>, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
+                           first_bucket, num_buckets);
+    else
+        hipLaunchKernelGGL(flush_kernel<false>, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
+                           first_bucket, num_buckets);
     return check_launch();
 }
 
@@ -1303,13 +1494,22 @@ static sh_status_t launch_all(sh_table *t, bool del, const uint32_t *keys, uint6
     if (waves > chunks)
         waves = chunks;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (del)
-        hipLaunchKernelGGL(all_kernel<true>, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
-                           keys, n, counts, nullptr, nullptr, 0,
-                           t->v.dup ? kEmptyPair : kTombPair);
+    const bool dup = (t->v.mode & SH_TABLE_DUPLICATES) != 0;
+    const bool ko = (t->v.mode & SH_TABLE_KEYS_ONLY) != 0;
+    // what a deleted slot becomes: a tombstone, or with duplicates an empty slot
+    const uint64_t gone = ko ? (dup ? kEmpty : kTombKey) : (dup ? kEmptyPair : kTombPair);
+    if (del && ko)
+        hipLaunchKernelGGL((all_kernel<true, true>), dim3(blocks), dim3(kBlock), 0, S(stream),
+                           t->v, keys, n, counts, nullptr, nullptr, 0, gone);
+    else if (del)
+        hipLaunchKernelGGL((all_kernel<true, false>), dim3(blocks), dim3(kBlock), 0, S(stream),
+                           t->v, keys, n, counts, nullptr, nullptr, 0, gone);
+    else if (ko)
+        hipLaunchKernelGGL((all_kernel<false, true>), dim3(blocks), dim3(kBlock), 0, S(stream),
+                           t->v, keys, n, counts, offsets, vals, cap, 0);
     else
-        hipLaunchKernelGGL(all_kernel<false>, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
-                           keys, n, counts, offsets, vals, cap, 0);
+        hipLaunchKernelGGL((all_kernel<false, false>), dim3(blocks), dim3(kBlock), 0, S(stream),
+                           t->v, keys, n, counts, offsets, vals, cap, 0);
     return check_launch();
 }
 
@@ -1394,7 +1594,8 @@ sh_status_t sh_set_launch(sh_table_t *t, const sh_launch_t *shape)
 sh_status_t sh_build(sh_table_t *t, const uint32_t *d_keys, const uint32_t *d_vals, uint64_t n,
                      uint8_t *d_status, void *stream)
 {
-    if (n && !d_vals)
+    const bool ko = t && (t->v.mode & SH_TABLE_KEYS_ONLY);
+    if (n && !d_vals && !ko) // a key-only table has no values to read
         return SH_EINVAL;
     return launch_ops<kInsert>(t, nullptr, d_keys, d_vals, n, nullptr, d_status, stream);
 }
@@ -1423,7 +1624,8 @@ sh_status_t sh_mixed(sh_table_t *t, const uint8_t *d_ops, const uint32_t *d_keys
                      const uint32_t *d_vals_in, uint64_t n, uint32_t *d_vals_out,
                      uint8_t *d_status, void *stream)
 {
-    if (n && (!d_ops || !d_vals_in || !d_vals_out || !d_status))
+    const bool ko = t && (t->v.mode & SH_TABLE_KEYS_ONLY);
+    if (n && (!d_ops || (!d_vals_in && !ko) || !d_vals_out || !d_status))
         return SH_EINVAL;
     return launch_ops<kMixed>(t, d_ops, d_keys, d_vals_in, n, d_vals_out, d_status, stream);
 }
@@ -1904,7 +2106,7 @@ sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uin
     const size_t need = sh_server_scratch_bytes(&c);
     if (!t || !out || !d_ops || !d_keys || !d_vals_in || !d_vals_out || !d_status ||
         n_ops == 0 || n_ops >= (1ull << 40) || !d_scratch || need == 0 ||
-        scratch_bytes < need || (reinterpret_cast<uintptr_t>(d_scratch) & 255u) || t->v.dup)
+        scratch_bytes < need || (reinterpret_cast<uintptr_t>(d_scratch) & 255u) || t->v.mode)
         return SH_EINVAL;
     sh_server *s = new (std::nothrow) sh_server();
     if (!s)

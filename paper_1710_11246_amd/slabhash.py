@@ -32,7 +32,7 @@ SH_BLOCK_SLABS = 2048
 SH_MAX_BATCHES = 4096
 
 
-SH_TABLE_DUPLICATES = 1
+SH_TABLE_DUPLICATES, SH_TABLE_KEYS_ONLY = 1, 2
 
 
 class ShParams(ctypes.Structure):
@@ -240,16 +240,17 @@ def sh_set_launch(t, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 
 
 
 def sh_build(t, keys, vals, status=None, stream=None) -> None:
+    """vals may be None for a key-only table (the library rejects it for key-value tables)."""
     n = keys.numel()
     _check("sh_build", lib().sh_build(
-        t, _dev(keys, "keys", _U32_TYPES), _dev(vals, "vals", _U32_TYPES, n), n,
+        t, _dev(keys, "keys", _U32_TYPES), _dev(vals, "vals", _U32_TYPES, n, True), n,
         _dev(status, "status", (torch.uint8,), n, True), _stream(stream)))
 
 
 def sh_insert(t, keys, vals, status=None, stream=None) -> None:
     n = keys.numel()
     _check("sh_insert", lib().sh_insert(
-        t, _dev(keys, "keys", _U32_TYPES), _dev(vals, "vals", _U32_TYPES, n), n,
+        t, _dev(keys, "keys", _U32_TYPES), _dev(vals, "vals", _U32_TYPES, n, True), n,
         _dev(status, "status", (torch.uint8,), n, True), _stream(stream)))
 
 
@@ -271,7 +272,8 @@ def sh_mixed(t, ops, keys, vals_in, vals_out, status, stream=None) -> None:
     n = keys.numel()
     _check("sh_mixed", lib().sh_mixed(
         t, _dev(ops, "ops", (torch.uint8,), n), _dev(keys, "keys", _U32_TYPES),
-        _dev(vals_in, "vals_in", _U32_TYPES, n), n, _dev(vals_out, "vals_out", _U32_TYPES, n),
+        _dev(vals_in, "vals_in", _U32_TYPES, n, True), n,
+        _dev(vals_out, "vals_out", _U32_TYPES, n),
         _dev(status, "status", (torch.uint8,), n), _stream(stream)))
 
 
@@ -479,9 +481,11 @@ class SlabHash:
     a table owned by a MultiSlabHash)."""
 
     def __init__(self, num_buckets: int, pool_slabs: int, hash_a: int, hash_b: int,
-                 device="cuda", stream=None, handle=None, owner=None, duplicates: bool = False):
+                 device="cuda", stream=None, handle=None, owner=None, duplicates: bool = False,
+                 keys_only: bool = False):
         self.params = ShParams(int(num_buckets), int(pool_slabs), int(hash_a), int(hash_b),
-                               SH_TABLE_DUPLICATES if duplicates else 0)
+                               (SH_TABLE_DUPLICATES if duplicates else 0)
+                               | (SH_TABLE_KEYS_ONLY if keys_only else 0))
         self.device = device
         self.owner = owner
         if handle is not None:
@@ -542,12 +546,12 @@ class SlabHash:
             count = self.num_buckets - first
         sh_flush(self.handle, first, count, stream)
 
-    def insert(self, keys, vals, stream=None, status=True):
+    def insert(self, keys, vals=None, stream=None, status=True):
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
         sh_insert(self.handle, keys, vals, st, stream)
         return st
 
-    def build(self, keys, vals, stream=None, status=True):
+    def build(self, keys, vals=None, stream=None, status=True):
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
         sh_build(self.handle, keys, vals, st, stream)
         return st

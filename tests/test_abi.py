@@ -33,7 +33,9 @@ def test_storage_bytes(lib):
     assert S.sh_storage_bytes(p) == want
     assert S.sh_storage_bytes(S.ShParams(1, 0, 1, 0)) == hdr + 256
     # invalid: zero buckets, pool not a multiple of 2048, a = 0, a >= p, b >= p, B + P too big
+    assert S.sh_storage_bytes(S.ShParams(16, 0, 3, 5, 3)) == S.sh_storage_bytes(S.ShParams(16, 0, 3, 5))
     for bad in [S.ShParams(0, 0, 1, 0), S.ShParams(8, 100, 1, 0), S.ShParams(8, 0, 0, 0),
+                S.ShParams(8, 0, 1, 0, 4), S.ShParams(8, 0, 1, 0, 0x80000000),
                 S.ShParams(8, 0, S.SH_HASH_PRIME, 0), S.ShParams(8, 0, 1, S.SH_HASH_PRIME),
                 S.ShParams(0xFFFFFFFF - 2048, 2048, 1, 0)]:
         assert S.sh_storage_bytes(bad) == 0
