@@ -524,6 +524,51 @@ def measure_duplicates(n_keys: int = 1 << 20, copies: int = 4, B: int = 217316,
     return out
 
 
+def measure_keys_only(B: int = 108658, reps: int = 5) -> dict:
+    """Key-only tables (the paper's 32-bit entries, 62 keys per slab): bulk build of 2^22
+    distinct keys into B buckets (utilisation about 0.6), then 2^22 all-hit and 2^22 all-miss
+    searches; median of `reps` runs on a reset table."""
+    import torch
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    n = 1 << 22
+    keys = W.distinct_keys(91, 0, n)
+    keys[keys == 0xFFFFFFFE] = W.distinct_keys(91, n, 1)[0]   # the deleted-entry marker
+    miss = W.distinct_keys(91, n + 1, n)
+    miss[miss == 0xFFFFFFFE] = W.distinct_keys(91, 2 * n + 1, 1)[0]
+    kd, qh = S.to_dev(keys), S.to_dev(keys[W.SplitMix64(92).permutation(n)])
+    qm = S.to_dev(miss)
+    rng = W.SplitMix64(93)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    t = S.SlabHash(B, S.pool_slabs_bound(n), a, b, keys_only=True)
+    st = torch.empty(n, dtype=torch.uint8, device="cuda")
+    vo = torch.empty(n, dtype=torch.int32, device="cuda")
+    fo = torch.empty(n, dtype=torch.uint8, device="cuda")
+    res = {"build": [], "search_hit": [], "search_miss": []}
+    for _ in range(reps):
+        t.reset()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        S.sh_build(t.handle, kd, None, st)
+        e[1].record()
+        S.sh_search(t.handle, qh, vo, fo)
+        e[2].record()
+        S.sh_search(t.handle, qm, vo, fo)
+        e[3].record()
+        torch.cuda.synchronize()
+        for i, k in enumerate(res):
+            res[k].append(e[i].elapsed_time(e[i + 1]))
+    assert bool((st == 1).all())
+    su = t.stats()
+    out = {"workload": "key-only: 2^22 distinct keys, B=%d, 62 keys per 256-byte slab" % B,
+           "utilisation": round(4.0 * su["live"] / (256.0 * su["slabs_total"]), 4)}
+    for k, v in res.items():
+        ms = float(np.median(v))
+        out[k + "_ms"] = round(ms, 4)
+        out[k + "_Mops"] = round(n / (ms * 1e-3) / 1e6, 1)
+    return out
+
+
 def measure_flush(table, keys, vals, st, stream, reps: int = 5) -> dict:
     """FLUSH of every bucket ("Flush" subsection) of the benchmark table after half of its 2^22
     keys have been deleted: median of `reps` runs, each on a freshly built and half-deleted
@@ -782,6 +827,8 @@ def main():
 
     log("duplicates")
     duplicates = measure_duplicates()
+    log("keys only")
+    keys_only = measure_keys_only()
 
     log("access-pattern ceilings")
     patterns = measure_patterns(int(table.storage.numel()), N_KEYS)
@@ -897,6 +944,7 @@ def main():
         "flush": flush,
         "allocator": allocator,
         "duplicates": duplicates,
+        "keys_only": keys_only,
         "cpu_baseline": cpu,
     }
     if sweep is not None:
