@@ -270,14 +270,37 @@ struct WaveLds {
     uint64_t msg[64];
 };
 
-// One chunk of up to 64 ops (lane l < count holds op base + l) on table T, processed in rounds
-// until every op has finished (see the description above).
-template <int K, bool Dup, bool KO>
-__device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
-                          const uint8_t *__restrict__ ops, const uint32_t *__restrict__ keys,
-                          const uint32_t *__restrict__ vals, uint32_t *__restrict__ vout,
-                          uint8_t *__restrict__ sout, uint64_t base, uint32_t count,
-                          uint32_t flags)
+// The inputs of one chunk, one op per lane (lanes past the chunk's end hold no op).
+struct ChunkIn {
+    uint32_t key, val, op;
+};
+
+template <int K, bool KO>
+__device__ __forceinline__ ChunkIn load_chunk(const uint8_t *__restrict__ ops,
+                                              const uint32_t *__restrict__ keys,
+                                              const uint32_t *__restrict__ vals, uint64_t base,
+                                              uint32_t count)
+{
+    const uint32_t lane = lane_id();
+    const bool in = lane < count;
+    ChunkIn c;
+    c.key = in ? keys[base + lane] : kEmpty;
+    c.val = 0;
+    if constexpr ((K == kInsert || K == kMixed) && !KO)
+        c.val = in ? vals[base + lane] : 0u;
+    c.op = (uint32_t)K;
+    if constexpr (K == kMixed)
+        c.op = in ? (uint32_t)ops[base + lane] : 0u;
+    return c;
+}
+
+// One chunk of up to 2 NQ ops (lane l < count holds op base + l, with inputs `c`) on table T,
+// processed in rounds until every op has finished (see the description above). NQ is the
+// number of op pairs, and so the length of each round's straight run of loads.
+template <int K, bool Dup, bool KO, int NQ = 32>
+__device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, ChunkIn c,
+                          uint32_t *__restrict__ vout, uint8_t *__restrict__ sout, uint64_t base,
+                          uint32_t count, uint32_t flags)
 {
     constexpr bool kCoherent = (K != kSearch);
     constexpr bool kHasIns = (K == kInsert || K == kMixed);
@@ -289,13 +312,7 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
     const uint64_t *lane_base = T.base + slot; // this lane's slot of slab 0
     const uint64_t i = base + lane;
     const bool in = lane < count;
-    const uint32_t key = in ? keys[i] : kEmpty;
-    uint32_t val = 0;
-    if constexpr (kHasIns && !KO)
-        val = in ? vals[i] : 0;
-    uint32_t op = (uint32_t)K;
-    if constexpr (K == kMixed)
-        op = in ? (uint32_t)ops[i] : 0u;
+    const uint32_t key = c.key, val = c.val, op = c.op;
     // key-only slabs reserve a second key, the deleted-entry marker
     const bool reserved = in && (key == kEmpty || (KO && key == kTombKey));
     const uint64_t res_m = ballot(reserved);
@@ -315,15 +332,15 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L,
         // ---- 1. load ----
         L.u[lane] = ((todo >> lane) & 1) ? ((loc == kEmpty) ? bkt : T.B + loc) : 0u;
         __builtin_amdgcn_wave_barrier();
-        uint64_t pre[32];
+        uint64_t pre[NQ];
 #pragma unroll
-        for (int q = 0; q < 32; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const uint32_t u = L.u[2 * q + half];
             pre[q] = load_slot<kCoherent>(lane_base + (size_t)u * 32);
         }
         // ---- 2. decide: the target lane of each op writes the op's outcome ----
 #pragma unroll
-        for (int q = 0; q < 32; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             if (!((todo >> (2 * q)) & 3ull))
                 continue;
             const uint64_t w = pre[q];
@@ -585,7 +602,7 @@ __device__ __forceinline__ void alloc_init(Alloc &al, uint32_t wave, uint32_t se
     al.rot = mix32(al.start) & 63u;
 }
 
-template <int K, bool Dup, bool KO>
+template <int K, bool Dup, bool KO, int NQ>
 __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__restrict__ ops,
                                                      const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ vals,
@@ -604,8 +621,8 @@ __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__re
     for (uint64_t c = wave; c < nchunks; c += nwaves) {
         const uint64_t base = c * C;
         const uint32_t count = (uint32_t)((n - base < C) ? n - base : C);
-        run_chunk<K, Dup, KO>(T, al, cnt, lds[wl_], ops, keys, vals, vout, sout, base, count,
-                              flags);
+        const ChunkIn cur = load_chunk<K, KO>(ops, keys, vals, base, count);
+        run_chunk<K, Dup, KO, NQ>(T, al, cnt, lds[wl_], cur, vout, sout, base, count, flags);
     }
     if (flags & kFlagCounters)
         flush_counters(T, cnt, al, wave);
@@ -693,8 +710,10 @@ __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ 
             count = 0; // range outside the op arrays: nothing is read or written
         else if (count > n_ops - base)
             count = n_ops - base;
-        run_chunk<kMixed, false, false>(Tv, al, cnt, lds[wl_], ops, keys, vals, vout, sout,
-                                        base, (uint32_t)count, flags);
+        run_chunk<kMixed, false, false>(
+            Tv, al, cnt, lds[wl_],
+            load_chunk<kMixed, false>(ops, keys, vals, base, (uint32_t)count), vout, sout, base,
+            (uint32_t)count, flags);
     }
     if ((flags & kFlagCounters) && cur_t != kEmpty)
         flush_counters(dir[cur_t], cnt, al, wave);
@@ -1218,15 +1237,16 @@ sh_status_t check_launch()
     return hipGetLastError() == hipSuccess ? SH_OK : SH_EHIP;
 }
 
-// Ops per wavefront: 64 (one per lane) unless that leaves fewer chunks than half the persistent
-// grid's wavefronts, then halved down to 8 so small batches still spread over the chip.
+// Ops per wavefront: 64 (one per lane) unless that leaves fewer chunks than the persistent
+// grid has wavefronts, then halved (down to 8) so small batches spread over the chip; a
+// wavefront's straight run of loads shrinks with its chunk (unique-key pair tables).
 uint32_t ops_per_wave_for(const sh_table *t, uint64_t n)
 {
     if (t->ops_per_wave)
         return t->ops_per_wave;
     const uint64_t waves = (uint64_t)t->num_cu * t->waves_per_cu;
     uint32_t C = 64;
-    while (C > 8 && 2 * ((n + C - 1) / C) < waves)
+    while (C > 8 && (n + C - 1) / C < waves)
         C >>= 1;
     return C;
 }
@@ -1273,22 +1293,38 @@ sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
     const uint32_t C = ops_per_wave_for(t, n);
     const dim3 grid(grid_for(t, n, C));
     const uint32_t seq = t->seq++;
-    switch (t->v.mode) {
-    case 0:
-        hipLaunchKernelGGL((ops_kernel<K, false, false>), grid, dim3(kBlock), 0, S(stream), t->v,
-                           ops, keys, vals, n, vout, sout, seq, C, t->flags);
+    // unique-key pair tables run a straight run of C / 2 loads per round; the other modes the
+    // full 32 (their chunks may still be shorter)
+    switch (t->v.mode == 0 ? C : 0u) {
+    case 64:
+        hipLaunchKernelGGL((ops_kernel<K, false, false, 32>), grid, dim3(kBlock), 0, S(stream),
+                           t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
         break;
-    case SH_TABLE_DUPLICATES:
-        hipLaunchKernelGGL((ops_kernel<K, true, false>), grid, dim3(kBlock), 0, S(stream), t->v,
-                           ops, keys, vals, n, vout, sout, seq, C, t->flags);
+    case 32:
+        hipLaunchKernelGGL((ops_kernel<K, false, false, 16>), grid, dim3(kBlock), 0, S(stream),
+                           t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
         break;
-    case SH_TABLE_KEYS_ONLY:
-        hipLaunchKernelGGL((ops_kernel<K, false, true>), grid, dim3(kBlock), 0, S(stream), t->v,
-                           ops, keys, vals, n, vout, sout, seq, C, t->flags);
+    case 16:
+        hipLaunchKernelGGL((ops_kernel<K, false, false, 8>), grid, dim3(kBlock), 0, S(stream),
+                           t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
+        break;
+    case 8:
+        hipLaunchKernelGGL((ops_kernel<K, false, false, 4>), grid, dim3(kBlock), 0, S(stream),
+                           t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
         break;
     default:
-        hipLaunchKernelGGL((ops_kernel<K, true, true>), grid, dim3(kBlock), 0, S(stream), t->v,
-                           ops, keys, vals, n, vout, sout, seq, C, t->flags);
+        if (t->v.mode == 0)
+            hipLaunchKernelGGL((ops_kernel<K, false, false, 32>), grid, dim3(kBlock), 0,
+                               S(stream), t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
+        else if (t->v.mode == SH_TABLE_DUPLICATES)
+            hipLaunchKernelGGL((ops_kernel<K, true, false, 32>), grid, dim3(kBlock), 0,
+                               S(stream), t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
+        else if (t->v.mode == SH_TABLE_KEYS_ONLY)
+            hipLaunchKernelGGL((ops_kernel<K, false, true, 32>), grid, dim3(kBlock), 0,
+                               S(stream), t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
+        else
+            hipLaunchKernelGGL((ops_kernel<K, true, true, 32>), grid, dim3(kBlock), 0,
+                               S(stream), t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
         break;
     }
     return check_launch();
@@ -1956,6 +1992,7 @@ struct sh_server {
     uint32_t seq = 0;
     bool stop = false;
     std::atomic<int> error{0};
+    std::atomic<uint64_t> completions{0}; // requests finished so far (read without the lock)
     std::thread thr;
 };
 
@@ -1995,6 +2032,7 @@ void server_loop(sh_server *s)
                 --s->unfinished;
                 R.t_done = now;
             }
+            s->completions.fetch_add(L.tickets.size(), std::memory_order_release);
             const int64_t a = s->base_allocated + (int64_t)(net - s->base_net);
             if (a > s->allocated)
                 s->allocated = a; // snapshots can lag one another; occupancy only grows
@@ -2217,17 +2255,25 @@ sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
     std::vector<uint64_t> outstanding;
     std::deque<uint64_t> backlog;
     uint64_t next = 0, finished = 0;
+    uint64_t seen = s->completions.load(std::memory_order_acquire);
+    // after a refusal for lack of room, admission can only succeed once requests finish
+    uint64_t refused_at = UINT64_MAX;
     const uint64_t t0 = clock_now_ns();
     while (finished < n) {
         const uint64_t now = clock_now_ns() - t0;
         while (next < n && h_arrival_ns[next] <= now)
             backlog.push_back(next++);
-        while (!backlog.empty()) {
+        while (!backlog.empty() &&
+               s->completions.load(std::memory_order_acquire) != refused_at) {
             const uint64_t i = backlog.front();
             uint64_t tk = 0;
+            const uint64_t before = s->completions.load(std::memory_order_acquire);
             const sh_status_t st = sh_server_submit(s, &h_reqs[i], &tk);
-            if (st == SH_EBUSY)
+            if (st == SH_EBUSY) {
+                refused_at = before;
                 break;
+            }
+            refused_at = UINT64_MAX;
             backlog.pop_front();
             if (st == SH_OK) {
                 ticket[i] = tk;
@@ -2240,7 +2286,13 @@ sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
                 return st;
             }
         }
-        if (!outstanding.empty()) {
+        // scan the outstanding requests only when the server has finished some since the last
+        // scan: the lock is the server thread's too
+        const uint64_t done_now = s->completions.load(std::memory_order_acquire);
+        if (!outstanding.empty() && done_now == seen)
+            std::this_thread::yield();
+        if (!outstanding.empty() && done_now != seen) {
+            seen = done_now;
             std::lock_guard<std::mutex> g(s->mu);
             for (size_t j = 0; j < outstanding.size();) {
                 const uint64_t i = outstanding[j];
