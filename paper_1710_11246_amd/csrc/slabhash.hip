@@ -635,6 +635,7 @@ __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__re
 // exclusive prefix sum in LDS; wavefront w then takes global chunks w, w + W, ... of the
 // concatenated chunk space and finds each chunk's descriptor by binary search. Nothing is
 // counted with atomics, so the launch can be captured in a graph and replayed as is.
+template <int NQ>
 __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ dir, uint32_t T,
                                                        const sh_batch_desc_t *__restrict__ desc,
                                                        uint32_t nb, uint64_t n_ops,
@@ -710,7 +711,7 @@ __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ 
             count = 0; // range outside the op arrays: nothing is read or written
         else if (count > n_ops - base)
             count = n_ops - base;
-        run_chunk<kMixed, false, false>(
+        run_chunk<kMixed, false, false, NQ>(
             Tv, al, cnt, lds[wl_],
             load_chunk<kMixed, false>(ops, keys, vals, base, (uint32_t)count), vout, sout, base,
             (uint32_t)count, flags);
@@ -1425,6 +1426,12 @@ size_t multi_layout(uint32_t T, const sh_params_t *p, size_t *offs)
 
 // One batched launch. n_ops bounds the op arrays; work_ops (the ops the descriptors actually
 // hold, or n_ops if unknown) sizes the grid and the ops per wavefront.
+uint32_t blocks_for(uint64_t waves)
+{
+    const uint64_t b = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    return b ? (uint32_t)b : 1u;
+}
+
 sh_status_t launch_multi_raw(const View *d_dir, uint32_t T, const sh_batch_desc_t *d_desc,
                              uint32_t nb, const uint8_t *d_ops, const uint32_t *d_keys,
                              const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,
@@ -1436,17 +1443,27 @@ sh_status_t launch_multi_raw(const View *d_dir, uint32_t T, const sh_batch_desc_
     const uint64_t waves = (uint64_t)num_cu * wpc;
     if (!C) {
         C = 64;
-        while (C > 8 && 2 * ((work_ops + C - 1) / C) < waves)
+        while (C > 8 && (work_ops + C - 1) / C < waves)
             C >>= 1;
     }
     uint64_t w = waves;
     const uint64_t chunks = (work_ops + C - 1) / C + nb; // at most one partial chunk each
     if (w > chunks)
         w = chunks;
-    const uint32_t blocks = (uint32_t)((w + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(multi_kernel, dim3(blocks ? blocks : 1), dim3(kBlock), 0, stream, d_dir,
-                       T, d_desc, nb, n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq,
-                       C, flags);
+    const dim3 grid(blocks_for(w));
+    // the straight run of loads is as long as a chunk's op pairs
+    if (C == 64)
+        hipLaunchKernelGGL(multi_kernel<32>, grid, dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
+                           n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
+    else if (C == 32)
+        hipLaunchKernelGGL(multi_kernel<16>, grid, dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
+                           n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
+    else if (C == 16)
+        hipLaunchKernelGGL(multi_kernel<8>, grid, dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
+                           n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
+    else
+        hipLaunchKernelGGL(multi_kernel<4>, grid, dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
+                           n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
     return check_launch();
 }
 
