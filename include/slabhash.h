@@ -83,10 +83,11 @@ typedef struct {
 
 /* Launch shape of the operation kernels. Never changes results.
    waves_per_cu: persistent grid of waves_per_cu * (compute units) wavefronts, at most 64
-                 (0 = library default, 16).
+                 (0 = the operation's default: 20 for inserts and deletes, 16 otherwise).
    ops_per_wave: operations each wavefront holds at a time, one per lane: 8, 16, 32 or 64
-                 (0 = chosen per call: 64, halved while the batch's chunks would not fill
-                 the grid).
+                 (0 = chosen per call: the operation's largest chunk, 16 for inserts and
+                 deletes, 32 for searches, 64 for mixed batches and for tables with flags,
+                 halved while the batch's chunks would not fill the grid).
    flags:        SH_LAUNCH_COUNTERS makes the operation kernels accumulate the counters that
                  sh_stats reports (off by default: it adds atomics at the end of each kernel). */
 enum { SH_LAUNCH_COUNTERS = 1u };

@@ -1188,7 +1188,7 @@ struct sh_table {
     size_t bytes;
     View v;
     uint32_t seq;
-    uint32_t waves_per_cu;
+    uint32_t waves_per_cu; // 0 = the operation kind's default
     uint32_t ops_per_wave; // 0 = chosen per call
     uint32_t flags;        // SH_LAUNCH_* bits
     int num_cu;
@@ -1238,24 +1238,55 @@ sh_status_t check_launch()
     return hipGetLastError() == hipSuccess ? SH_OK : SH_EHIP;
 }
 
-// Ops per wavefront: 64 (one per lane) unless that leaves fewer chunks than the persistent
-// grid has wavefronts, then halved (down to 8) so small batches spread over the chip; a
-// wavefront's straight run of loads shrinks with its chunk (unique-key pair tables).
-uint32_t ops_per_wave_for(const sh_table *t, uint64_t n)
+// Default launch shape of an operation kind: wavefronts per compute unit and the largest chunk
+// (ops per wavefront). A persistent grid should not exceed the wavefronts that fit at once at
+// the kernel's register use, or the ones that do not fit run after the others. For unique-key
+// pair tables the straight run of loads follows the chunk: inserts and deletes at 16 ops per
+// wavefront use 80 VGPRs (24 wavefronts fit per CU) and ran fastest at 20 per CU (2^22-pair
+// build 254 us against 330 us at 64 ops and 16 per CU); searches ran fastest at 32 ops, 16 per
+// CU (72 VGPRs). The other modes run the full 32-load straight run (about 128 VGPRs: 16 fit).
+struct Shape {
+    uint32_t waves_per_cu, max_ops;
+};
+
+Shape default_shape(const sh_table *t, int kind)
+{
+    if (t->v.mode != 0)
+        return {kDefaultWavesPerCU, 64};
+    switch (kind) {
+    case kSearch:
+        return {16, 32};
+    case kInsert:
+    case kDelete:
+        return {20, 16};
+    default:
+        return {kDefaultWavesPerCU, 64};
+    }
+}
+
+uint32_t waves_per_cu_for(const sh_table *t, int kind)
+{
+    return t->waves_per_cu ? t->waves_per_cu : default_shape(t, kind).waves_per_cu;
+}
+
+// Ops per wavefront: the kind's largest chunk, halved (down to 8) while the batch's chunks would
+// not fill the persistent grid, so small batches spread over the chip; a wavefront's straight
+// run of loads shrinks with its chunk (unique-key pair tables).
+uint32_t ops_per_wave_for(const sh_table *t, uint64_t n, int kind)
 {
     if (t->ops_per_wave)
         return t->ops_per_wave;
-    const uint64_t waves = (uint64_t)t->num_cu * t->waves_per_cu;
-    uint32_t C = 64;
+    const uint64_t waves = (uint64_t)t->num_cu * waves_per_cu_for(t, kind);
+    uint32_t C = default_shape(t, kind).max_ops;
     while (C > 8 && (n + C - 1) / C < waves)
         C >>= 1;
     return C;
 }
 
-uint32_t grid_for(const sh_table *t, uint64_t n, uint32_t C)
+uint32_t grid_for(const sh_table *t, uint64_t n, uint32_t C, int kind)
 {
     const uint64_t chunks = (n + C - 1) / C;
-    uint64_t waves = (uint64_t)t->num_cu * t->waves_per_cu;
+    uint64_t waves = (uint64_t)t->num_cu * waves_per_cu_for(t, kind);
     if (waves > chunks)
         waves = chunks;
     if (waves == 0)
@@ -1291,8 +1322,8 @@ sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
         return SH_OK;
     if (n >= (1ull << 32) || !keys)
         return SH_EINVAL;
-    const uint32_t C = ops_per_wave_for(t, n);
-    const dim3 grid(grid_for(t, n, C));
+    const uint32_t C = ops_per_wave_for(t, n, K);
+    const dim3 grid(grid_for(t, n, C, K));
     const uint32_t seq = t->seq++;
     // unique-key pair tables run a straight run of C / 2 loads per round; the other modes the
     // full 32 (their chunks may still be shorter)
@@ -1387,7 +1418,7 @@ void bind_table(sh_table *t, const sh_params_t *p, char *storage, size_t bytes, 
     t->storage = storage;
     t->bytes = bytes;
     t->num_cu = ncu;
-    t->waves_per_cu = kDefaultWavesPerCU;
+    t->waves_per_cu = 0; // 0: the operation kind's default
     t->ops_per_wave = 0;
     t->flags = 0;
     t->seq = 0;
@@ -1542,7 +1573,8 @@ static sh_status_t launch_all(sh_table *t, bool del, const uint32_t *keys, uint6
                               uint32_t *counts, const uint64_t *offsets, uint32_t *vals,
                               uint64_t cap, void *stream)
 {
-    uint64_t waves = (uint64_t)t->num_cu * t->waves_per_cu;
+    // 32-load straight runs, like the full-width operation kernels
+    uint64_t waves = (uint64_t)t->num_cu * (t->waves_per_cu ? t->waves_per_cu : kDefaultWavesPerCU);
     const uint64_t chunks = (n + 63) / 64;
     if (waves > chunks)
         waves = chunks;
@@ -1629,7 +1661,7 @@ sh_status_t sh_set_launch(sh_table_t *t, const sh_launch_t *shape)
     if (!t)
         return SH_EINVAL;
     if (!shape) {
-        t->waves_per_cu = kDefaultWavesPerCU;
+        t->waves_per_cu = 0;
         t->ops_per_wave = 0;
         t->flags = 0;
         return SH_OK;
@@ -1638,7 +1670,7 @@ sh_status_t sh_set_launch(sh_table_t *t, const sh_launch_t *shape)
     if (shape->waves_per_cu > 64 || (c != 0 && c != 8 && c != 16 && c != 32 && c != 64) ||
         (shape->flags & ~(uint32_t)SH_LAUNCH_COUNTERS))
         return SH_EINVAL;
-    t->waves_per_cu = shape->waves_per_cu ? shape->waves_per_cu : kDefaultWavesPerCU;
+    t->waves_per_cu = shape->waves_per_cu; // 0: the operation kind's default
     t->ops_per_wave = c;
     t->flags = shape->flags;
     return SH_OK;
@@ -2085,7 +2117,8 @@ void server_loop(sh_server *s)
                                      hipMemcpyHostToDevice, L.stream) == hipSuccess;
             ok = ok && launch_multi_raw(s->d_dir, 1, L.d_desc, nb, s->ops, s->keys, s->vals,
                                         s->vout, s->sout, s->n_ops, work, s->t->num_cu,
-                                        s->t->waves_per_cu, s->t->ops_per_wave, s->seq++,
+                                        waves_per_cu_for(s->t, kMixed), s->t->ops_per_wave,
+                                        s->seq++,
                                         kFlagCounters, L.stream) == SH_OK;
             ok = ok && hipMemcpyAsync(L.h_cnt, s->t->v.counters, kCounterBytes,
                                       hipMemcpyDeviceToHost, L.stream) == hipSuccess;
