@@ -648,8 +648,9 @@ def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
     a buffer of nbytes (the benchmark table's size): n_ops random 256-byte slab reads (the
     pattern of a search that finds its key in the base slab), n_ops random 64-bit
     compare-and-swaps, and n_ops slab reads each followed by a compare-and-swap into the slab
-    (the pattern of an insert). Each is the median of `reps` runs at the faster of two launch
-    shapes; the buffer is refilled with all ones before every run."""
+    (the pattern of an insert). Each is the median of `reps` runs at the fastest of 12 launch
+    shapes (8 to 32 wavefronts per CU) and depths (1 to 16 op pairs or swaps in flight per
+    wavefront iteration); the buffer is refilled with all ones before every run."""
     import torch
     from paper_1710_11246_amd import roofs as R
     buf = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda")
@@ -657,23 +658,25 @@ def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
     for name, kind in (("slab_load", R.SH_ROOF_SLAB_LOAD), ("cas", R.SH_ROOF_CAS),
                        ("load_cas", R.SH_ROOF_LOAD_CAS)):
         best = None
-        for wpc in (16, 32):
-            ts = []
-            for r in range(reps + 1):
-                buf.fill_(-1)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                R.sh_roof_run(kind, buf, n_ops, wpc, seed=17 * r + 1)
-                e1.record()
-                torch.cuda.synchronize()
-                if r:
-                    ts.append(e0.elapsed_time(e1) * 1e3)
-            t = float(np.median(ts))
-            if best is None or t < best[0]:
-                best = (t, wpc)
+        for wpc in (8, 16, 24, 32):
+            for depth in (1, 4, 16):
+                ts = []
+                for r in range(reps + 1):
+                    buf.fill_(-1)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    R.sh_roof_run(kind, buf, n_ops, wpc, seed=17 * r + 1, depth=depth)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    if r:
+                        ts.append(e0.elapsed_time(e1) * 1e3)
+                t = float(np.median(ts))
+                if best is None or t < best[0]:
+                    best = (t, wpc, depth)
         res[name + "_us"] = round(best[0], 1)
         res[name + "_waves_per_cu"] = best[1]
+        res[name + "_depth"] = best[2]
     del buf
     return res
 

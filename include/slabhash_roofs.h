@@ -37,12 +37,15 @@ enum { SH_ROOF_SLAB_LOAD = 0, SH_ROOF_CAS = 1, SH_ROOF_LOAD_CAS = 2 };
    default stream); asynchronous.
    d_buf:        device buffer, 256-byte aligned, caller-owned.
    bytes:        a multiple of 256, at least 256, at most (2^32 - 1) * 256.
-   n_ops:        below 2^32; 0 is a no-op.
+   n_ops:        below 2^32 - 64; 0 is a no-op.
    waves_per_cu: persistent grid of waves_per_cu * (compute units) wavefronts, 1..64 (0 = 32).
+   depth:        operations in flight per wavefront iteration: the slab patterns issue the loads
+                 of `depth` op pairs before using any; the swap pattern issues `depth` swaps per
+                 lane back to back. 1, 4, 8 or 16 (0 = 8).
    Returns SH_EINVAL for a bad kind or argument (nothing enqueued), SH_EHIP if the device query
    or the launch fails, else SH_OK. */
 sh_status_t sh_roof_run(int kind, void *d_buf, size_t bytes, uint64_t n_ops,
-                        uint32_t waves_per_cu, uint32_t seed, void *stream);
+                        uint32_t waves_per_cu, uint32_t depth, uint32_t seed, void *stream);
 
 #ifdef __cplusplus
 }

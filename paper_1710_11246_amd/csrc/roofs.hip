@@ -42,8 +42,10 @@ __device__ __forceinline__ void sink(uint64_t *buf, uint64_t acc)
         buf[0] = acc;
 }
 
-// Two operations per wavefront iteration: lanes 0..31 read slab of op 2p, lanes 32..63 of 2p+1.
-template <bool Cas>
+// P op pairs per wavefront iteration: lanes 0..31 read the slab of op 2p, lanes 32..63 that of
+// op 2p+1, for the P pairs p of a group; all P loads are issued before any is used (then, with
+// Cas, one swap per op), so P pairs' reads are in flight per wavefront.
+template <bool Cas, int P>
 __global__ __launch_bounds__(kBlock) void slab_kernel(uint64_t *buf, uint32_t slabs, uint32_t n,
                                                       uint32_t seed)
 {
@@ -51,46 +53,76 @@ __global__ __launch_bounds__(kBlock) void slab_kernel(uint64_t *buf, uint32_t sl
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const uint32_t pairs = (uint32_t)(((uint64_t)n + 1) / 2);
+    const uint32_t groups = (pairs + P - 1) / P;
     uint64_t acc = 0;
-    for (uint32_t p = wave; p < pairs; p += nwaves) {
-        const uint32_t op = 2 * p + (lane >> 5);
-        const bool live = op < n;
-        const uint32_t s = __umulhi(mix(seed + op), slabs);
-        uint64_t *slab = buf + (size_t)s * 32;
-        const uint64_t w = load_coherent(slab + (lane & 31u));
-        acc += w;
-        if constexpr (Cas) {
-            const uint64_t m = __ballot(w == ~0ull);
-            const uint32_t hm = (uint32_t)(m >> (lane & 32u)) & 0x7FFFFFFFu;
-            if (live && (lane & 31u) == 0)
-                acc += cas(slab + (hm ? __builtin_ctz(hm) : 0u), ~0ull, (uint64_t)op);
+    for (uint32_t g = wave; g < groups; g += nwaves) {
+        uint64_t w[P];
+        uint32_t s[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const uint32_t op = 2 * (g * P + j) + (lane >> 5); // < 2 * groups * P <= n + 2 P
+            s[j] = __umulhi(mix(seed + op), slabs);
+            w[j] = load_coherent(buf + (size_t)s[j] * 32 + (lane & 31u));
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            acc += w[j];
+            if constexpr (Cas) {
+                const uint32_t op = 2 * (g * P + j) + (lane >> 5);
+                const uint64_t m = __ballot(w[j] == ~0ull);
+                const uint32_t hm = (uint32_t)(m >> (lane & 32u)) & 0x7FFFFFFFu;
+                if (op < n && (lane & 31u) == 0)
+                    acc += cas(buf + (size_t)s[j] * 32 + (hm ? __builtin_ctz(hm) : 0u), ~0ull,
+                               (uint64_t)op);
+            }
         }
     }
     sink(buf, acc);
 }
 
-// One compare-and-swap per lane per iteration.
+// P compare-and-swaps per lane per iteration (ops i, i + nt, ..., issued back to back).
+template <int P>
 __global__ __launch_bounds__(kBlock) void cas_kernel(uint64_t *buf, uint32_t slabs, uint32_t n,
                                                      uint32_t seed)
 {
     const uint32_t nt = gridDim.x * blockDim.x;
     uint64_t acc = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nt) {
-        const uint32_t h = mix(seed + i);
-        uint64_t *p = buf + (size_t)__umulhi(h, slabs) * 32 + (mix(h) & 31u);
-        acc += cas(p, ~0ull, (uint64_t)i);
+    for (uint64_t i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += (uint64_t)nt * P) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const uint64_t i = i0 + (uint64_t)j * nt;
+            if (i < n) {
+                const uint32_t h = mix(seed + (uint32_t)i);
+                uint64_t *p = buf + (size_t)__umulhi(h, slabs) * 32 + (mix(h) & 31u);
+                acc += cas(p, ~0ull, i);
+            }
+        }
     }
     sink(buf, acc);
+}
+
+template <int P>
+void launch_pattern(int kind, dim3 grid, hipStream_t s, uint64_t *buf, uint32_t slabs, uint32_t n,
+                    uint32_t seed)
+{
+    if (kind == SH_ROOF_SLAB_LOAD)
+        hipLaunchKernelGGL((slab_kernel<false, P>), grid, dim3(kBlock), 0, s, buf, slabs, n, seed);
+    else if (kind == SH_ROOF_LOAD_CAS)
+        hipLaunchKernelGGL((slab_kernel<true, P>), grid, dim3(kBlock), 0, s, buf, slabs, n, seed);
+    else
+        hipLaunchKernelGGL((cas_kernel<P>), grid, dim3(kBlock), 0, s, buf, slabs, n, seed);
 }
 
 } // namespace
 
 extern "C" sh_status_t sh_roof_run(int kind, void *d_buf, size_t bytes, uint64_t n_ops,
-                                   uint32_t waves_per_cu, uint32_t seed, void *stream)
+                                   uint32_t waves_per_cu, uint32_t depth, uint32_t seed,
+                                   void *stream)
 {
     if (kind < SH_ROOF_SLAB_LOAD || kind > SH_ROOF_LOAD_CAS || !d_buf ||
         (reinterpret_cast<uintptr_t>(d_buf) & 255u) || bytes < 256 || (bytes & 255u) ||
-        bytes / 256 > 0xFFFFFFFFull || n_ops >= (1ull << 32) || waves_per_cu > 64)
+        bytes / 256 > 0xFFFFFFFFull || n_ops >= (1ull << 32) - 64 || waves_per_cu > 64 ||
+        (depth != 0 && depth != 1 && depth != 4 && depth != 8 && depth != 16))
         return SH_EINVAL;
     if (n_ops == 0)
         return SH_OK;
@@ -104,13 +136,19 @@ extern "C" sh_status_t sh_roof_run(int kind, void *d_buf, size_t bytes, uint64_t
     uint64_t *buf = static_cast<uint64_t *>(d_buf);
     const uint32_t slabs = (uint32_t)(bytes / 256), n = (uint32_t)n_ops;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (kind == SH_ROOF_SLAB_LOAD)
-        hipLaunchKernelGGL(slab_kernel<false>, dim3(blocks), dim3(kBlock), 0, s, buf, slabs, n,
-                           seed);
-    else if (kind == SH_ROOF_LOAD_CAS)
-        hipLaunchKernelGGL(slab_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, buf, slabs, n,
-                           seed);
-    else
-        hipLaunchKernelGGL(cas_kernel, dim3(blocks), dim3(kBlock), 0, s, buf, slabs, n, seed);
+    switch (depth ? depth : 8u) {
+    case 1:
+        launch_pattern<1>(kind, dim3(blocks), s, buf, slabs, n, seed);
+        break;
+    case 4:
+        launch_pattern<4>(kind, dim3(blocks), s, buf, slabs, n, seed);
+        break;
+    case 8:
+        launch_pattern<8>(kind, dim3(blocks), s, buf, slabs, n, seed);
+        break;
+    default:
+        launch_pattern<16>(kind, dim3(blocks), s, buf, slabs, n, seed);
+        break;
+    }
     return hipGetLastError() == hipSuccess ? SH_OK : SH_EHIP;
 }

@@ -19,7 +19,8 @@ SH_ROOF_SLAB_LOAD, SH_ROOF_CAS, SH_ROOF_LOAD_CAS = 0, 1, 2
 
 _SIGS = {
     "sh_roof_run": ([ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64,
-                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int),
+                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p],
+                    ctypes.c_int),
 }
 _lib = None
 
@@ -47,14 +48,14 @@ def declared_symbols() -> list[str]:
 
 
 def sh_roof_run(kind: int, buf: torch.Tensor, n_ops: int, waves_per_cu: int = 0, seed: int = 1,
-                stream=None) -> None:
+                stream=None, depth: int = 0) -> None:
     """Enqueue n_ops operations of pattern `kind` over the device tensor `buf` (its bytes,
     rounded down to whole 256-byte slabs)."""
     if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.is_contiguous()):
         raise ValueError("buf must be a contiguous device tensor")
     nbytes = (buf.numel() * buf.element_size()) // 256 * 256
     code = lib().sh_roof_run(int(kind), ctypes.c_void_p(buf.data_ptr()), nbytes, int(n_ops),
-                             int(waves_per_cu), int(seed) & 0xFFFFFFFF,
+                             int(waves_per_cu), int(depth), int(seed) & 0xFFFFFFFF,
                              ctypes.c_void_p(_stream(stream)))
     if code != SH_OK:
         raise SlabHashError("sh_roof_run", code)

@@ -133,10 +133,12 @@ def test_roofs_library_exports_and_argument_errors():
     assert declared == ["sh_roof_run"] and set(declared) == set(R._SIGS)
     assert hasattr(rl, "sh_roof_run")
     buf = ctypes.c_void_p(1 << 20)  # aligned stand-in; every call below fails before using it
-    bad = [(7, buf, 1 << 20, 10, 0), (-1, buf, 1 << 20, 10, 0), (0, None, 1 << 20, 10, 0),
-           (0, ctypes.c_void_p((1 << 20) + 8), 1 << 20, 10, 0), (0, buf, 100, 10, 0),
-           (0, buf, 300, 10, 0), (0, buf, 1 << 20, 1 << 32, 0), (0, buf, 1 << 20, 10, 65)]
-    for kind, p, nbytes, n, wpc in bad:
-        assert rl.sh_roof_run(kind, p, nbytes, n, wpc, 1, None) == S.SH_EINVAL
+    bad = [(7, buf, 1 << 20, 10, 0, 0), (-1, buf, 1 << 20, 10, 0, 0),
+           (0, None, 1 << 20, 10, 0, 0), (0, ctypes.c_void_p((1 << 20) + 8), 1 << 20, 10, 0, 0),
+           (0, buf, 100, 10, 0, 0), (0, buf, 300, 10, 0, 0), (0, buf, 1 << 20, 1 << 32, 0, 0),
+           (0, buf, 1 << 20, (1 << 32) - 64, 0, 0), (0, buf, 1 << 20, 10, 65, 0),
+           (0, buf, 1 << 20, 10, 0, 3), (0, buf, 1 << 20, 10, 0, 32)]
+    for kind, p, nbytes, n, wpc, depth in bad:
+        assert rl.sh_roof_run(kind, p, nbytes, n, wpc, depth, 1, None) == S.SH_EINVAL
     # no operations: nothing is enqueued and no device is touched
-    assert rl.sh_roof_run(1, buf, 1 << 20, 0, 0, 1, None) == S.SH_OK
+    assert rl.sh_roof_run(1, buf, 1 << 20, 0, 0, 0, 1, None) == S.SH_OK

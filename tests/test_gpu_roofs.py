@@ -29,7 +29,7 @@ def _gpu():
 def test_cas_pattern_addresses():
     slabs, n, seed = 4099, 20000, 12345
     buf = torch.full((slabs * 32,), -1, dtype=torch.int64, device="cuda")
-    R.sh_roof_run(R.SH_ROOF_CAS, buf, n, 8, seed)
+    R.sh_roof_run(R.SH_ROOF_CAS, buf, n, 8, seed, depth=4)
     got = buf.cpu().numpy().view(np.uint64)
     i = np.arange(n, dtype=np.uint64)
     h = mix(i + seed)
@@ -46,7 +46,7 @@ def test_cas_pattern_addresses():
 def test_load_cas_pattern_slabs():
     slabs, n, seed = 1031, 5001, 777
     buf = torch.full((slabs * 32,), -1, dtype=torch.int64, device="cuda")
-    R.sh_roof_run(R.SH_ROOF_LOAD_CAS, buf, n, 4, seed)
+    R.sh_roof_run(R.SH_ROOF_LOAD_CAS, buf, n, 4, seed, depth=16)
     got = buf.cpu().numpy().view(np.uint64).reshape(slabs, 32)
     ops = np.arange(n, dtype=np.uint64)
     slab_of = (mix(ops + seed) * slabs) >> 32
