@@ -41,9 +41,9 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
 # Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
 # a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
-TRAFFIC_SRC_SHA = "45d37ced5ee93ce1"
-TRAFFIC_BYTES = {"build": 1464884072, "search_hit": 1038301361, "search_miss": 1038301361,
-                 "mixed": 19381186, "reset": 94022308}
+TRAFFIC_SRC_SHA = "c37f337dc4cd708b"
+TRAFFIC_BYTES = {"build": 1358583986, "search_hit": 1038974697, "search_miss": 1038974697,
+                 "mixed": 19381344, "reset": 94022363}
 
 
 def source_sha() -> str:
