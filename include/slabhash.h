@@ -348,7 +348,10 @@ sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uin
    range outside the op arrays or an empty request. */
 sh_status_t sh_server_submit(sh_server_t *s, const sh_request_t *req, uint64_t *ticket);
 
-/* *done = 1 once the request's results are in device memory; times on sh_clock_ns's clock. */
+/* *done = 1 once the request's results are in device memory; times on sh_clock_ns's clock.
+   A server remembers the last 2^20 tickets; an older ticket whose finish has been reported (by a
+   poll that returned *done = 1, or by sh_server_replay) expires and gives SH_EINVAL, as does any
+   finished ticket 2^22 or more behind the newest. */
 sh_status_t sh_server_poll(sh_server_t *s, uint64_t ticket, int *done, uint64_t *t_admit_ns,
                            uint64_t *t_done_ns);
 

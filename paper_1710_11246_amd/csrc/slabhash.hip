@@ -1999,10 +1999,14 @@ uint64_t clock_now_ns()
         .count();
 }
 
+constexpr size_t kTicketWindow = size_t(1) << 20; // finished requests a server remembers
+constexpr uint32_t kReplayBurst = 1024;         // submissions between scans of a load driver
+
 struct ServerReq {
     sh_request_t r;
     uint64_t t_admit;
     uint64_t t_done; // 0 = not finished (guarded by the server mutex)
+    bool read;       // its finish has been reported (poll or load driver)
 };
 
 struct LaunchSlot {
@@ -2031,7 +2035,8 @@ struct sh_server {
     uint32_t nslots = 0;
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<ServerReq> reqs;   // indexed by ticket
+    std::deque<ServerReq> reqs;   // request of ticket t at reqs[t - reqs_base]
+    uint64_t reqs_base = 0;       // ticket of reqs.front(); older tickets have expired
     std::deque<uint64_t> pending; // admitted, not yet launched
     uint64_t unfinished = 0;      // admitted, not yet finished
     int64_t reserved = 0;         // slabs promised to unfinished requests
@@ -2076,7 +2081,7 @@ void server_loop(sh_server *s)
             const long long net = counters_net(L.h_cnt);
             std::lock_guard<std::mutex> g(s->mu);
             for (uint64_t tk : L.tickets) {
-                ServerReq &R = s->reqs[tk];
+                ServerReq &R = s->reqs[tk - s->reqs_base];
                 s->reserved -= R.r.inserts;
                 --s->unfinished;
                 R.t_done = now;
@@ -2099,7 +2104,7 @@ void server_loop(sh_server *s)
             {
                 std::lock_guard<std::mutex> g(s->mu);
                 while (!s->pending.empty() && nb < kMaxBatches) {
-                    const ServerReq &R = s->reqs[s->pending.front()];
+                    const ServerReq &R = s->reqs[s->pending.front() - s->reqs_base];
                     if (nb > 0 && work + R.r.length > s->cfg.max_batch_ops)
                         break;
                     L.h_desc[nb].offset = R.r.offset;
@@ -2264,12 +2269,21 @@ sh_status_t sh_server_submit(sh_server_t *s, const sh_request_t *req, uint64_t *
         return SH_EBUSY;
     s->reserved += req->inserts;
     ++s->unfinished;
+    // Finished requests beyond the last kTicketWindow tickets are forgotten once their finish
+    // has been reported (their tickets expire), and beyond four windows even if it has not, so
+    // a long-running server holds bounded memory.
+    while (s->reqs.size() >= kTicketWindow && s->reqs.front().t_done != 0 &&
+           (s->reqs.front().read || s->reqs.size() >= 4 * kTicketWindow)) {
+        s->reqs.pop_front();
+        ++s->reqs_base;
+    }
     s->reqs.emplace_back();
     ServerReq &R = s->reqs.back();
     R.r = *req;
     R.t_admit = clock_now_ns();
     R.t_done = 0;
-    *ticket = s->reqs.size() - 1;
+    R.read = false;
+    *ticket = s->reqs_base + s->reqs.size() - 1;
     s->pending.push_back(*ticket);
     s->cv.notify_one();
     return SH_OK;
@@ -2281,10 +2295,12 @@ sh_status_t sh_server_poll(sh_server_t *s, uint64_t ticket, int *done, uint64_t 
     if (!s || !done)
         return SH_EINVAL;
     std::lock_guard<std::mutex> g(s->mu);
-    if (ticket >= s->reqs.size())
+    if (ticket < s->reqs_base || ticket - s->reqs_base >= s->reqs.size())
         return SH_EINVAL;
-    const ServerReq &R = s->reqs[ticket];
+    ServerReq &R = s->reqs[ticket - s->reqs_base];
     *done = R.t_done != 0;
+    if (*done)
+        R.read = true;
     if (t_admit_ns)
         *t_admit_ns = R.t_admit;
     if (t_done_ns)
@@ -2313,8 +2329,10 @@ sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
         const uint64_t now = clock_now_ns() - t0;
         while (next < n && h_arrival_ns[next] <= now)
             backlog.push_back(next++);
-        while (!backlog.empty() &&
-               s->completions.load(std::memory_order_acquire) != refused_at) {
+        // submit in bursts so the scan below runs (and reads finished tickets) between them
+        for (uint32_t burst = 0; burst < kReplayBurst && !backlog.empty() &&
+                                 s->completions.load(std::memory_order_acquire) != refused_at;
+             ++burst) {
             const uint64_t i = backlog.front();
             uint64_t tk = 0;
             const uint64_t before = s->completions.load(std::memory_order_acquire);
@@ -2346,8 +2364,14 @@ sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
             std::lock_guard<std::mutex> g(s->mu);
             for (size_t j = 0; j < outstanding.size();) {
                 const uint64_t i = outstanding[j];
-                const uint64_t td = s->reqs[ticket[i]].t_done;
+                // a ticket of this driver expires only if millions of later requests finished
+                // before it was scanned; it then counts as finished now
+                const bool gone = ticket[i] < s->reqs_base;
+                ServerReq *R = gone ? nullptr : &s->reqs[ticket[i] - s->reqs_base];
+                const uint64_t td = gone ? clock_now_ns() : R->t_done;
                 if (td) {
+                    if (R)
+                        R->read = true;
                     h_done_ns[i] = td - t0;
                     ++finished;
                     outstanding[j] = outstanding.back();

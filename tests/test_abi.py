@@ -142,3 +142,14 @@ def test_roofs_library_exports_and_argument_errors():
         assert rl.sh_roof_run(kind, p, nbytes, n, wpc, depth, 1, None) == S.SH_EINVAL
     # no operations: nothing is enqueued and no device is touched
     assert rl.sh_roof_run(1, buf, 1 << 20, 0, 0, 0, 1, None) == S.SH_OK
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with a message before touching a
+    device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr

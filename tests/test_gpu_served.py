@@ -187,3 +187,29 @@ def test_admission(oracle_mod):
     assert (st == 1).all()
     s = t.stats()
     assert s["live"] == 2000 and s["violations"] == 0 and s["error_word"] == 0
+
+
+def test_tickets_expire_after_the_window(oracle_mod):
+    """A server remembers the last 2^20 tickets: after 2^20 + 2^17 one-op requests, the first
+    tickets (whose finish the load driver has read) have expired, the newest still answer, and
+    every request's results are in place."""
+    say("case: served ticket window")
+    rng = W.SplitMix64(401)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    t = S.SlabHash(4099, 2048, a, b)
+    keys = W.unique_keys(rng, 1 << 16)
+    vals = W.value_of(keys)
+    t.build(S.to_dev(keys), S.to_dev(vals))
+    n = (1 << 20) + (1 << 17)
+    q = keys[rng.below(n, keys.size)]
+    ops = np.zeros(n, np.uint8)
+    with S.Server(t, S.to_dev(ops), S.to_dev(q), S.to_dev(q)) as srv:
+        adm, done = srv.replay(np.arange(n), np.ones(n, np.uint32), np.zeros(n, np.uint32),
+                               np.zeros(n, np.uint64))
+        with pytest.raises(S.SlabHashError):
+            srv.poll(0)
+        assert srv.poll(n - 1)[0]
+        srv.stop()
+        gv, gs = S.to_host_u32(srv.vals_out), srv.status.cpu().numpy()
+    assert (done != np.iinfo(np.uint64).max).all() and (gs == 1).all()
+    assert (gv == W.value_of(q)).all()
