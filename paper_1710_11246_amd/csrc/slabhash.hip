@@ -82,6 +82,25 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ uint32_t ffs0(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
 
+// This lane's bit of a wave-uniform lane mask (no instruction: the mask is used as the lane
+// condition directly).
+__device__ __forceinline__ bool inverse_ballot(uint64_t m)
+{
+    return __builtin_amdgcn_inverse_ballot_w64(m);
+}
+
+// Lanes holding a slot of a slab: every lane but slot 31 of each half (the next index).
+constexpr uint64_t kSlotLanes = ~((1ull << 31) | (1ull << 63));
+
+// A wave-uniform 64-bit value kept in scalar registers. (The builtin returns int: each half is
+// taken back to uint32_t before widening, or the low half would be sign-extended.)
+__device__ __forceinline__ uint64_t uniform64(uint64_t x)
+{
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // v_writelane_b32: lane `j` of x takes the wave-uniform value v (bound to the LLVM intrinsic so
 // the compiler still schedules and checks hazards around it).
 extern "C" __device__ uint32_t sh_llvm_writelane(uint32_t v, uint32_t j, uint32_t x)
@@ -328,6 +347,7 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
     uint32_t loc = kEmpty;        // this lane's cursor
     uint64_t todo = ballot(act);
     while (todo) {
+        todo = uniform64(todo);
         ++cnt.rounds;
         // ---- 1. load ----
         L.u[lane] = ((todo >> lane) & 1) ? ((loc == kEmpty) ? bkt : T.B + loc) : 0u;
@@ -344,14 +364,20 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
             if (!((todo >> (2 * q)) & 3ull))
                 continue;
             const uint64_t w = pre[q];
-            const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+            const uint32_t lo = (uint32_t)w;
+            uint32_t hi = (uint32_t)(w >> 32);
+            // keep `hi` a 32-bit register value, so tests on it stay 32-bit compares
+            asm("" : "+v"(hi));
             const uint32_t kq = L.key[2 * q + half];
             // a key-value slab holds one pair per lane (key in lo); a key-only slab two keys per
             // lane, entries 2 slot (lo) and 2 slot + 1 (hi)
-            const bool mlo = !is31 && lo == kq;
-            const bool mhi = KO && !is31 && hi == kq;
+            // votes come straight from the compares (slot 31 holds the next index, not a pair)
+            const uint64_t mlo_m = ballot(lo == kq) & kSlotLanes;
+            const uint64_t mhi_m = KO ? (ballot(hi == kq) & kSlotLanes) : 0ull;
+            const bool mlo = inverse_ballot(mlo_m);
+            const bool mhi = KO && inverse_ballot(mhi_m);
             const bool match = mlo || mhi;
-            const uint32_t kh = (uint32_t)(ballot(match) >> hshift); // my half's key votes
+            const uint32_t kh = (uint32_t)((mlo_m | mhi_m) >> hshift); // my half's key votes
             // the op's slot is the first match of the slab (with unique keys the only one)
             const bool is_key = Dup ? (match && (kh & below) == 0u) : match;
             const uint32_t kslot = KO ? (mlo ? 2 * slot : 2 * slot + 1) : slot;
@@ -368,10 +394,13 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
             uint32_t code, tslot = slot;
             uint32_t empties = 0;
             if constexpr (kHasIns) {
-                const bool elo = !is31 && (KO ? lo == kEmpty : w == kEmptyPair);
-                const bool ehi = KO && !is31 && hi == kEmpty;
+                const uint64_t elo_m = (KO ? ballot(lo == kEmpty) : ballot(w == kEmptyPair)) &
+                                       kSlotLanes;
+                const uint64_t ehi_m = KO ? (ballot(hi == kEmpty) & kSlotLanes) : 0ull;
+                const bool elo = inverse_ballot(elo_m);
+                const bool ehi = KO && inverse_ballot(ehi_m);
                 const bool is_empty = elo || ehi;
-                const uint32_t eh = (uint32_t)(ballot(is_empty) >> hshift);
+                const uint32_t eh = (uint32_t)((elo_m | ehi_m) >> hshift);
                 empties = eh;
                 const bool first_empty = ins && is_empty && (eh & below) == 0u;
                 const bool tail = is31 && (!ins || eh == 0u);

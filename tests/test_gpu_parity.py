@@ -103,6 +103,40 @@ def test_ragged_sizes(oracle_mod, n):
     assert_same_table(t, o)
 
 
+@pytest.mark.parametrize("opw", [8, 16, 32, 64])
+def test_every_chunk_width(oracle_mod, opw):
+    """Each chunk width, with a ragged last chunk: lanes past a chunk's end hold no op and must
+    touch nothing. (A 32-op chunk once let lanes 32..63 act whenever op 31 was pending; their
+    default key and value then filled bucket 0's list with (EMPTY, 0) pairs.)"""
+    say("case: chunk width %d" % opw)
+    n = 37 * 64 + 33
+    rng = W.SplitMix64(700 + opw)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    keys = W.unique_keys(rng, 2 * n)
+    ins, extra = keys[:n], keys[n:]
+    t, o = make(oracle_mod, 61, a, b, S.pool_slabs_bound(3 * n))
+    t.set_launch(0, opw)
+    st = t.build(S.to_dev(ins), S.to_dev(W.value_of(ins)))
+    assert (st.cpu().numpy() == o.replace(ins, W.value_of(ins))).all()
+    assert_same_table(t, o)
+    search_both(t, o, keys)
+    gone = ins[::3]
+    assert (t.delete(S.to_dev(gone)).cpu().numpy() == o.delete(gone)).all()
+    assert_same_table(t, o)
+    present = np.setdiff1d(ins, gone)
+    n_ins, n_del, n_hit, n_miss = W.gamma_counts(n, W.GAMMAS["gamma1"])
+    ops, mk, mv = W.mixed_batch(rng, present, extra[:n_ins], extra[n_ins:], n_ins, n_del, n_hit,
+                                n_miss)
+    pre_v, pre_f, _ = o.search(mk)
+    gv, gs = t.mixed(S.to_dev(ops), S.to_dev(mk), S.to_dev(mv))
+    ov, ost = o.mixed(ops, mk, mv)
+    post_v, post_f, _ = o.search(mk)
+    LZ.check_single_mutation_batch(ops, mk, S.to_host_u32(gv), gs.cpu().numpy(), pre_f, pre_v,
+                                   post_f, post_v, ost)
+    st = assert_same_table(t, o)
+    assert st["tombstones"] == int(o.bucket_stats()[1].sum())
+
+
 def test_empty_calls_are_noops(oracle_mod):
     say("case: empty inputs")
     t, o = make(oracle_mod, 16, 3, 5, 0)
