@@ -800,7 +800,10 @@ def main():
     new_slabs = stats_built["pool_allocated"]
     build_counters = {k: stats_built[k] for k in
                       ("rounds", "cas_lost", "allocs", "link_lost", "block_moves")}
-    build_counters["rounds_per_chunk"] = round(stats_built["rounds"] / (N_KEYS / 64), 4)
+    build_wpc, build_opw = table.launch_shape(S.SH_OP_INSERT, N_KEYS)
+    build_counters["ops_per_wave"] = build_opw
+    build_counters["rounds_per_chunk"] = round(
+        stats_built["rounds"] / -(-N_KEYS // build_opw), 4)
     S.sh_set_launch(h, args.waves_per_cu, 0, 0)
     util = 8.0 * stats_built["live"] / (256.0 * stats_built["slabs_total"])
 

@@ -83,7 +83,9 @@ typedef struct {
 
 /* Launch shape of the operation kernels. Never changes results.
    waves_per_cu: persistent grid of waves_per_cu * (compute units) wavefronts, at most 64
-                 (0 = the operation's default: 20 for inserts and deletes, 16 otherwise).
+                 (0 = the operation's default: 20 for inserts and deletes, 16 otherwise,
+                 lowered to the wavefronts of the chosen kernel that fit on a compute unit at
+                 once; a value set here is used as given).
    ops_per_wave: operations each wavefront holds at a time, one per lane: 8, 16, 32 or 64
                  (0 = chosen per call: the operation's largest chunk, 16 for inserts and
                  deletes, 32 for searches, 64 for mixed batches and for tables with flags,
@@ -164,6 +166,16 @@ sh_status_t sh_destroy(sh_table_t *t);
 /* Set the launch shape used by later calls on this table (NULL restores the default).
    Out-of-range fields give SH_EINVAL. */
 sh_status_t sh_set_launch(sh_table_t *t, const sh_launch_t *shape);
+
+/* The launch shape a call of n operations of one kind would use on this table now, after
+   sh_set_launch and the defaults above: kind is SH_OP_SEARCH, SH_OP_INSERT (build and insert),
+   SH_OP_DELETE, or SH_KIND_MIXED (sh_mixed). *waves_per_cu and *ops_per_wave receive the
+   wavefronts per compute unit of the persistent grid and the ops each wavefront holds at a
+   time; the grid is the smaller of that many wavefronts and the batch's chunks. Host-only.
+   A NULL argument or an unknown kind gives SH_EINVAL. */
+enum { SH_KIND_MIXED = 3 };
+sh_status_t sh_launch_shape(const sh_table_t *t, int kind, uint64_t n, uint32_t *waves_per_cu,
+                            uint32_t *ops_per_wave);
 
 /* Bulk build: insert n pairs, each lane of a wavefront holding one ("Bulk benchmarks"; the
    paper notes a bulk build and an incremental batch insertion are the same operation). Uses
@@ -297,6 +309,7 @@ sh_status_t sh_multi_graph(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_
 /* Replay a captured graph on `stream`. */
 sh_status_t sh_graph_launch(sh_graph_t *g, void *stream);
 
+/* Free the graph and its handle; SH_EHIP if HIP reported an error while destroying it. */
 sh_status_t sh_graph_destroy(sh_graph_t *g);
 
 /* Free the host objects only; the device storage stays the caller's. */

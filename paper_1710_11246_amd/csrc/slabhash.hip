@@ -51,6 +51,9 @@ constexpr uint32_t kMaxBatches = SH_MAX_BATCHES;
 constexpr uint32_t kDefaultWavesPerCU = 16;
 
 enum Kind { kSearch = 0, kInsert = 1, kDelete = 2, kMixed = 3 };
+static_assert(kSearch == SH_OP_SEARCH && kInsert == SH_OP_INSERT && kDelete == SH_OP_DELETE &&
+                  kMixed == SH_KIND_MIXED,
+              "kernel kinds are the public operation codes");
 
 struct Header {
     uint32_t err;
@@ -1312,10 +1315,39 @@ uint32_t ops_per_wave_for(const sh_table *t, uint64_t n, int kind)
     return C;
 }
 
-uint32_t grid_for(const sh_table *t, uint64_t n, uint32_t C, int kind)
+// Wavefronts of kernel `fn` that fit on one compute unit at once (its registers and LDS), from
+// the occupancy API, cached per kernel; 64 (no limit) if the query fails.
+uint32_t resident_waves_per_cu(const void *fn)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, uint32_t>> cache;
+    std::lock_guard<std::mutex> g(mu);
+    for (const auto &e : cache)
+        if (e.first == fn)
+            return e.second;
+    int nb = 0;
+    uint32_t w = 64;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) == hipSuccess && nb > 0)
+        w = (uint32_t)nb * kWavesPerBlock;
+    cache.emplace_back(fn, w);
+    return w;
+}
+
+// Waves per CU of a persistent launch of `fn`: the caller's explicit choice (set > 0) as given;
+// else the default, lowered to what fits at once, so no wavefront waits for another to finish
+// its whole share.
+uint32_t launch_wpc(uint32_t set, uint32_t dflt, const void *fn)
+{
+    if (set)
+        return set;
+    const uint32_t r = resident_waves_per_cu(fn);
+    return r < dflt ? r : dflt;
+}
+
+uint32_t grid_for(const sh_table *t, uint64_t n, uint32_t C, uint32_t wpc)
 {
     const uint64_t chunks = (n + C - 1) / C;
-    uint64_t waves = (uint64_t)t->num_cu * waves_per_cu_for(t, kind);
+    uint64_t waves = (uint64_t)t->num_cu * wpc;
     if (waves > chunks)
         waves = chunks;
     if (waves == 0)
@@ -1340,6 +1372,30 @@ sh_status_t launch_init(sh_table *t, void *stream)
     return check_launch();
 }
 
+using OpsFn = void (*)(View, const uint8_t *, const uint32_t *, const uint32_t *, uint64_t,
+                      uint32_t *, uint8_t *, uint32_t, uint32_t, uint32_t);
+
+// The operation kernel for kind K on table t at C ops per wavefront: unique-key pair tables run
+// a straight run of C / 2 loads per round, the other modes the full 32 (their chunks may still
+// be shorter).
+template <int K>
+OpsFn ops_fn(const sh_table *t, uint32_t C)
+{
+    switch (t->v.mode) {
+    case 0:
+        return C == 64 ? ops_kernel<K, false, false, 32>
+                       : C == 32 ? ops_kernel<K, false, false, 16>
+                                 : C == 16 ? ops_kernel<K, false, false, 8>
+                                           : ops_kernel<K, false, false, 4>;
+    case SH_TABLE_DUPLICATES:
+        return ops_kernel<K, true, false, 32>;
+    case SH_TABLE_KEYS_ONLY:
+        return ops_kernel<K, false, true, 32>;
+    default:
+        return ops_kernel<K, true, true, 32>;
+    }
+}
+
 template <int K>
 sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
                        const uint32_t *vals, uint64_t n, uint32_t *vout, uint8_t *sout,
@@ -1352,42 +1408,13 @@ sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
     if (n >= (1ull << 32) || !keys)
         return SH_EINVAL;
     const uint32_t C = ops_per_wave_for(t, n, K);
-    const dim3 grid(grid_for(t, n, C, K));
+    const OpsFn fn = ops_fn<K>(t, C);
+    const uint32_t wpc =
+        launch_wpc(t->waves_per_cu, default_shape(t, K).waves_per_cu, reinterpret_cast<const void *>(fn));
+    const dim3 grid(grid_for(t, n, C, wpc));
     const uint32_t seq = t->seq++;
-    // unique-key pair tables run a straight run of C / 2 loads per round; the other modes the
-    // full 32 (their chunks may still be shorter)
-    switch (t->v.mode == 0 ? C : 0u) {
-    case 64:
-        hipLaunchKernelGGL((ops_kernel<K, false, false, 32>), grid, dim3(kBlock), 0, S(stream),
-                           t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
-        break;
-    case 32:
-        hipLaunchKernelGGL((ops_kernel<K, false, false, 16>), grid, dim3(kBlock), 0, S(stream),
-                           t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
-        break;
-    case 16:
-        hipLaunchKernelGGL((ops_kernel<K, false, false, 8>), grid, dim3(kBlock), 0, S(stream),
-                           t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
-        break;
-    case 8:
-        hipLaunchKernelGGL((ops_kernel<K, false, false, 4>), grid, dim3(kBlock), 0, S(stream),
-                           t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
-        break;
-    default:
-        if (t->v.mode == 0)
-            hipLaunchKernelGGL((ops_kernel<K, false, false, 32>), grid, dim3(kBlock), 0,
-                               S(stream), t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
-        else if (t->v.mode == SH_TABLE_DUPLICATES)
-            hipLaunchKernelGGL((ops_kernel<K, true, false, 32>), grid, dim3(kBlock), 0,
-                               S(stream), t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
-        else if (t->v.mode == SH_TABLE_KEYS_ONLY)
-            hipLaunchKernelGGL((ops_kernel<K, false, true, 32>), grid, dim3(kBlock), 0,
-                               S(stream), t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
-        else
-            hipLaunchKernelGGL((ops_kernel<K, true, true, 32>), grid, dim3(kBlock), 0,
-                               S(stream), t->v, ops, keys, vals, n, vout, sout, seq, C, t->flags);
-        break;
-    }
+    hipLaunchKernelGGL(fn, grid, dim3(kBlock), 0, S(stream), t->v, ops, keys, vals, n, vout, sout,
+                       seq, C, t->flags);
     return check_launch();
 }
 
@@ -1492,6 +1519,11 @@ uint32_t blocks_for(uint64_t waves)
     return b ? (uint32_t)b : 1u;
 }
 
+using MultiFn = void (*)(const View *, uint32_t, const sh_batch_desc_t *, uint32_t, uint64_t,
+                        const uint8_t *, const uint32_t *, const uint32_t *, uint32_t *,
+                        uint8_t *, uint32_t, uint32_t, uint32_t);
+
+// One batched launch; wpc = 0 takes the default waves per CU (lowered to what fits at once).
 sh_status_t launch_multi_raw(const View *d_dir, uint32_t T, const sh_batch_desc_t *d_desc,
                              uint32_t nb, const uint8_t *d_ops, const uint32_t *d_keys,
                              const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,
@@ -1500,30 +1532,23 @@ sh_status_t launch_multi_raw(const View *d_dir, uint32_t T, const sh_batch_desc_
                              hipStream_t stream)
 {
     uint32_t C = ops_per_wave;
-    const uint64_t waves = (uint64_t)num_cu * wpc;
     if (!C) {
+        const uint64_t waves = (uint64_t)num_cu * (wpc ? wpc : kDefaultWavesPerCU);
         C = 64;
         while (C > 8 && (work_ops + C - 1) / C < waves)
             C >>= 1;
     }
-    uint64_t w = waves;
+    // the straight run of loads is as long as a chunk's op pairs
+    const MultiFn fn = C == 64 ? multi_kernel<32>
+                               : C == 32 ? multi_kernel<16>
+                                         : C == 16 ? multi_kernel<8> : multi_kernel<4>;
+    uint64_t w = (uint64_t)num_cu *
+                 launch_wpc(wpc, kDefaultWavesPerCU, reinterpret_cast<const void *>(fn));
     const uint64_t chunks = (work_ops + C - 1) / C + nb; // at most one partial chunk each
     if (w > chunks)
         w = chunks;
-    const dim3 grid(blocks_for(w));
-    // the straight run of loads is as long as a chunk's op pairs
-    if (C == 64)
-        hipLaunchKernelGGL(multi_kernel<32>, grid, dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
-                           n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
-    else if (C == 32)
-        hipLaunchKernelGGL(multi_kernel<16>, grid, dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
-                           n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
-    else if (C == 16)
-        hipLaunchKernelGGL(multi_kernel<8>, grid, dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
-                           n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
-    else
-        hipLaunchKernelGGL(multi_kernel<4>, grid, dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
-                           n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
+    hipLaunchKernelGGL(fn, dim3(blocks_for(w)), dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
+                       n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
     return check_launch();
 }
 
@@ -1705,6 +1730,22 @@ sh_status_t sh_set_launch(sh_table_t *t, const sh_launch_t *shape)
     return SH_OK;
 }
 
+sh_status_t sh_launch_shape(const sh_table_t *t, int kind, uint64_t n, uint32_t *waves_per_cu,
+                            uint32_t *ops_per_wave)
+{
+    if (!t || !waves_per_cu || !ops_per_wave || kind < kSearch || kind > kMixed)
+        return SH_EINVAL;
+    const uint32_t C = ops_per_wave_for(t, n, kind);
+    const OpsFn fn = kind == kSearch   ? ops_fn<kSearch>(t, C)
+                     : kind == kInsert ? ops_fn<kInsert>(t, C)
+                     : kind == kDelete ? ops_fn<kDelete>(t, C)
+                                       : ops_fn<kMixed>(t, C);
+    *waves_per_cu = launch_wpc(t->waves_per_cu, default_shape(t, kind).waves_per_cu,
+                               reinterpret_cast<const void *>(fn));
+    *ops_per_wave = C;
+    return SH_OK;
+}
+
 sh_status_t sh_build(sh_table_t *t, const uint32_t *d_keys, const uint32_t *d_vals, uint64_t n,
                      uint8_t *d_status, void *stream)
 {
@@ -1830,7 +1871,7 @@ sh_status_t sh_multi_create(uint32_t T, const sh_params_t *h_params, void *d_sto
     m->bytes = bytes;
     m->d_dir = reinterpret_cast<View *>(d_storage);
     m->num_cu = ncu;
-    m->waves_per_cu = kDefaultWavesPerCU;
+    m->waves_per_cu = 0; // the default
     sh_status_t s = SH_OK;
     for (uint32_t t = 0; t < T && s == SH_OK; ++t) {
         Layout L;
@@ -1869,7 +1910,7 @@ sh_status_t sh_multi_set_launch(sh_multi_t *m, const sh_launch_t *shape)
     if (!m)
         return SH_EINVAL;
     if (!shape) {
-        m->waves_per_cu = kDefaultWavesPerCU;
+        m->waves_per_cu = 0;
         m->ops_per_wave = 0;
         m->flags = 0;
         return SH_OK;
@@ -1878,7 +1919,7 @@ sh_status_t sh_multi_set_launch(sh_multi_t *m, const sh_launch_t *shape)
     if (shape->waves_per_cu > 64 || (c != 0 && c != 8 && c != 16 && c != 32 && c != 64) ||
         (shape->flags & ~(uint32_t)SH_LAUNCH_COUNTERS))
         return SH_EINVAL;
-    m->waves_per_cu = shape->waves_per_cu ? shape->waves_per_cu : kDefaultWavesPerCU;
+    m->waves_per_cu = shape->waves_per_cu; // 0: the default
     m->ops_per_wave = c;
     m->flags = shape->flags;
     return SH_OK;
@@ -1953,13 +1994,13 @@ sh_status_t sh_multi_graph(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_
             if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
                 s = SH_EHIP;
         } else if (graph) {
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph); // best effort on the error path
         }
     }
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     if (s != SH_OK) {
         if (g->graph)
-            hipGraphDestroy(g->graph);
+            (void)hipGraphDestroy(g->graph);
         free(g);
         return s;
     }
@@ -1978,10 +2019,10 @@ sh_status_t sh_graph_destroy(sh_graph_t *g)
 {
     if (!g)
         return SH_EINVAL;
-    hipGraphExecDestroy(g->exec);
-    hipGraphDestroy(g->graph);
+    bool ok = hipGraphExecDestroy(g->exec) == hipSuccess;
+    ok = (hipGraphDestroy(g->graph) == hipSuccess) && ok;
     free(g);
-    return SH_OK;
+    return ok ? SH_OK : SH_EHIP;
 }
 
 sh_status_t sh_multi_destroy(sh_multi_t *m)
@@ -2091,7 +2132,8 @@ long long counters_net(const unsigned long long *cs)
 
 void server_loop(sh_server *s)
 {
-    hipSetDevice(s->device);
+    if (hipSetDevice(s->device) != hipSuccess)
+        s->error.store(1);
     for (;;) {
         bool progressed = false, any_busy = false;
         // completed launches: stamp their requests, release reservations, refresh occupancy
@@ -2151,7 +2193,7 @@ void server_loop(sh_server *s)
                                      hipMemcpyHostToDevice, L.stream) == hipSuccess;
             ok = ok && launch_multi_raw(s->d_dir, 1, L.d_desc, nb, s->ops, s->keys, s->vals,
                                         s->vout, s->sout, s->n_ops, work, s->t->num_cu,
-                                        waves_per_cu_for(s->t, kMixed), s->t->ops_per_wave,
+                                        s->t->waves_per_cu, s->t->ops_per_wave,
                                         s->seq++,
                                         kFlagCounters, L.stream) == SH_OK;
             ok = ok && hipMemcpyAsync(L.h_cnt, s->t->v.counters, kCounterBytes,
@@ -2174,18 +2216,19 @@ void server_loop(sh_server *s)
     }
 }
 
+// Release a server's slots (best effort: nothing is left to report a failure to).
 void server_free(sh_server *s)
 {
     for (uint32_t k = 0; k < s->nslots; ++k) {
         LaunchSlot &L = s->slots[k];
         if (L.ev)
-            hipEventDestroy(L.ev);
+            (void)hipEventDestroy(L.ev);
         if (L.stream)
-            hipStreamDestroy(L.stream);
+            (void)hipStreamDestroy(L.stream);
         if (L.h_desc)
-            hipHostFree(L.h_desc);
+            (void)hipHostFree(L.h_desc);
         if (L.h_cnt)
-            hipHostFree(L.h_cnt);
+            (void)hipHostFree(L.h_cnt);
     }
     delete s;
 }

@@ -23,6 +23,7 @@ HEADER_PATH = os.path.join(os.path.dirname(PKG), "include", "slabhash.h")
 
 SH_OK, SH_EINVAL, SH_ENOMEM, SH_EHIP, SH_EBUSY = 0, 1, 2, 3, 4
 SH_OP_SEARCH, SH_OP_INSERT, SH_OP_DELETE = 0, 1, 2
+SH_KIND_MIXED = 3
 SH_ERR_RESERVED_KEY, SH_ERR_POOL_EXHAUSTED = 1, 2
 SH_EMPTY_KEY = 0xFFFFFFFF
 SH_HASH_PRIME = 4294967291
@@ -89,6 +90,7 @@ _SIGS = {
     "sh_free_slabs": ([_P, _P, _U64, _P], ctypes.c_int),
     "sh_destroy": ([_P], ctypes.c_int),
     "sh_set_launch": ([_P, _P], ctypes.c_int),
+    "sh_launch_shape": ([_P, ctypes.c_int, ctypes.c_uint64, _P, _P], ctypes.c_int),
     "sh_build": ([_P, _P, _P, _U64, _P, _P], ctypes.c_int),
     "sh_insert": ([_P, _P, _P, _U64, _P, _P], ctypes.c_int),
     "sh_delete": ([_P, _P, _U64, _P, _P], ctypes.c_int),
@@ -237,6 +239,14 @@ def sh_destroy(t) -> None:
 def sh_set_launch(t, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0) -> None:
     shape = ShLaunch(int(waves_per_cu), int(ops_per_wave), int(flags))
     _check("sh_set_launch", lib().sh_set_launch(t, ctypes.byref(shape)))
+
+
+def sh_launch_shape(t, kind: int, n: int) -> tuple[int, int]:
+    """(waves per CU, ops per wavefront) that a call of n ops of `kind` would use now."""
+    w, c = ctypes.c_uint32(), ctypes.c_uint32()
+    _check("sh_launch_shape", lib().sh_launch_shape(t, int(kind), int(n), ctypes.byref(w),
+                                                    ctypes.byref(c)))
+    return int(w.value), int(c.value)
 
 
 def sh_build(t, keys, vals, status=None, stream=None) -> None:
@@ -516,6 +526,9 @@ class SlabHash:
 
     def set_launch(self, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0):
         sh_set_launch(self.handle, waves_per_cu, ops_per_wave, flags)
+
+    def launch_shape(self, kind: int, n: int) -> tuple[int, int]:
+        return sh_launch_shape(self.handle, kind, n)
 
     def search_all(self, keys, stream=None):
         """SEARCHALL of each key: (counts, offsets, values) as device tensors, query i's values

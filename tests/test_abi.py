@@ -64,6 +64,8 @@ def test_argument_errors_before_any_device_call(lib):
     assert lib.sh_free_slabs(None, 256, 10, None) == S.SH_EINVAL
     assert lib.sh_destroy(None) == S.SH_EINVAL
     assert lib.sh_set_launch(None, None) == S.SH_EINVAL
+    w, c = ctypes.c_uint32(), ctypes.c_uint32()
+    assert lib.sh_launch_shape(None, 0, 10, ctypes.byref(w), ctypes.byref(c)) == S.SH_EINVAL
 
 
 def test_strerror(lib):

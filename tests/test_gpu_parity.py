@@ -137,6 +137,28 @@ def test_every_chunk_width(oracle_mod, opw):
     assert st["tombstones"] == int(o.bucket_stats()[1].sum())
 
 
+def test_launch_shape_reports_the_shape_used():
+    """The shape query follows sh_set_launch and the per-kind defaults: a set shape is reported
+    as set; by default small batches get the smallest chunk (whose kernel fits at least as many
+    wavefronts per CU as the largest), default grids never exceed 20 wavefronts per CU, and bad
+    arguments are refused."""
+    t = S.SlabHash(97, 2048, 3, 5)
+    kinds = (S.SH_OP_SEARCH, S.SH_OP_INSERT, S.SH_OP_DELETE, S.SH_KIND_MIXED)
+    for kind in kinds:
+        w, c = t.launch_shape(kind, 1 << 22)
+        assert 1 <= w <= 20 and c in (8, 16, 32, 64)
+        w8, c8 = t.launch_shape(kind, 100)
+        assert c8 == 8 and w <= w8 <= 20
+    t.set_launch(12, 32)
+    assert all(t.launch_shape(k, n) == (12, 32) for k in kinds for n in (1, 1 << 22))
+    t.set_launch()
+    assert t.launch_shape(S.SH_OP_INSERT, 100)[1] == 8
+    with pytest.raises(S.SlabHashError):
+        t.launch_shape(4, 10)
+    with pytest.raises(S.SlabHashError):
+        t.launch_shape(-1, 10)
+
+
 def test_empty_calls_are_noops(oracle_mod):
     say("case: empty inputs")
     t, o = make(oracle_mod, 16, 3, 5, 0)
