@@ -41,9 +41,9 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
 # Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
 # a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
-TRAFFIC_SRC_SHA = "499cbbb7a1fb4777"
-TRAFFIC_BYTES = {"build": 1358614741, "search_hit": 1038912699, "search_miss": 1038912699,
-                 "mixed": 19381404, "reset": 94022427}
+TRAFFIC_SRC_SHA = "64b613fbf3b93cd3"
+TRAFFIC_BYTES = {"build": 1355561969, "search_hit": 1039072572, "search_miss": 1039072572,
+                 "mixed": 19375133, "reset": 94022372}
 
 
 def source_sha() -> str:
