@@ -1627,28 +1627,29 @@ static sh_status_t launch_all(sh_table *t, bool del, const uint32_t *keys, uint6
                               uint32_t *counts, const uint64_t *offsets, uint32_t *vals,
                               uint64_t cap, void *stream)
 {
-    // 32-load straight runs, like the full-width operation kernels
-    uint64_t waves = (uint64_t)t->num_cu * (t->waves_per_cu ? t->waves_per_cu : kDefaultWavesPerCU);
-    const uint64_t chunks = (n + 63) / 64;
-    if (waves > chunks)
-        waves = chunks;
-    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    using AllFn = void (*)(View, const uint32_t *, uint64_t, uint32_t *, const uint64_t *,
+                           uint32_t *, uint64_t, uint64_t);
     const bool dup = (t->v.mode & SH_TABLE_DUPLICATES) != 0;
     const bool ko = (t->v.mode & SH_TABLE_KEYS_ONLY) != 0;
     // what a deleted slot becomes: a tombstone, or with duplicates an empty slot
     const uint64_t gone = ko ? (dup ? kEmpty : kTombKey) : (dup ? kEmptyPair : kTombPair);
-    if (del && ko)
-        hipLaunchKernelGGL((all_kernel<true, true>), dim3(blocks), dim3(kBlock), 0, S(stream),
-                           t->v, keys, n, counts, nullptr, nullptr, 0, gone);
-    else if (del)
-        hipLaunchKernelGGL((all_kernel<true, false>), dim3(blocks), dim3(kBlock), 0, S(stream),
-                           t->v, keys, n, counts, nullptr, nullptr, 0, gone);
-    else if (ko)
-        hipLaunchKernelGGL((all_kernel<false, true>), dim3(blocks), dim3(kBlock), 0, S(stream),
-                           t->v, keys, n, counts, offsets, vals, cap, 0);
+    const AllFn fn = del ? (ko ? all_kernel<true, true> : all_kernel<true, false>)
+                         : (ko ? all_kernel<false, true> : all_kernel<false, false>);
+    // 32-load straight runs, like the full-width operation kernels; the default grid is what
+    // fits at once at these kernels' register use
+    uint64_t waves = (uint64_t)t->num_cu *
+                     launch_wpc(t->waves_per_cu, kDefaultWavesPerCU,
+                                reinterpret_cast<const void *>(fn));
+    const uint64_t chunks = (n + 63) / 64;
+    if (waves > chunks)
+        waves = chunks;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (del)
+        hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, S(stream), t->v, keys, n, counts,
+                           nullptr, nullptr, 0, gone);
     else
-        hipLaunchKernelGGL((all_kernel<false, false>), dim3(blocks), dim3(kBlock), 0, S(stream),
-                           t->v, keys, n, counts, offsets, vals, cap, 0);
+        hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, S(stream), t->v, keys, n, counts,
+                           offsets, vals, cap, 0);
     return check_launch();
 }
 
