@@ -888,8 +888,9 @@ __global__ __launch_bounds__(kBlock) void walk_kernel(View T, uint32_t *__restri
     }
 }
 
-// FLUSH ("Flush" subsection): one wavefront per bucket of [first, first + count), grid-stride.
-// The wavefront walks the bucket's list head to tail and moves its live pairs, in the order it
+// FLUSH ("Flush" subsection): each half-wavefront takes one bucket of [first, first + count)
+// (lanes 0..31 bucket 2p, lanes 32..63 bucket 2p + 1, p grid-stride), so a wavefront walks two
+// lists at once. A half walks its bucket's list head to tail and moves its live pairs, in the order it
 // meets them, to the front of the list. The slab that receives the last live pair (the base
 // slab if there is none) becomes the tail: its remaining slots are emptied and its next index
 // cleared. The slabs after it are reset to all ones, so a later allocation finds them empty, and
@@ -906,10 +907,16 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
     constexpr uint32_t kCap = KO ? kKeyEntries : 31u;
     const uint32_t lane = lane_id();
     const uint32_t slot = lane & 31;
+    const uint32_t half = lane >> 5, hshift = lane & 32;
     const uint32_t below = (1u << slot) - 1u;
     const uint32_t wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    for (uint32_t i = wave; i < count; i += nwaves) {
+    // slot 31 of this half's slab (its next index lives in the high word)
+    auto last_of_half = [&](uint32_t v) { return half ? rl(v, 63) : rl(v, 31); };
+    for (uint32_t p = wave; (uint64_t)2 * p < count; p += nwaves) {
+        const uint32_t i = 2 * p + half;
+        if (i >= count)
+            continue; // an odd count leaves the last wavefront's upper half idle
         const uint32_t bkt = first + i;
         uint32_t ru = bkt;         // unified index of the slab being read
         uint32_t wu = bkt, ws = 0; // write position: slot ws of slab wu (kCap = wu is full)
@@ -918,12 +925,12 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
         bool ok = true;
         for (;;) {
             w = T.base[(size_t)ru * 32 + slot];
-            nxt = rl((uint32_t)(w >> 32), 31);
+            nxt = last_of_half((uint32_t)(w >> 32));
             const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
             const bool live = slot < 31 && lo != kEmpty && (!KO || lo != kTombKey);
             const bool live_hi = KO && slot < 31 && hi != kEmpty && hi != kTombKey;
-            const uint32_t lm = (uint32_t)ballot(live); // lanes 0..31; 32..63 mirror them
-            const uint32_t hm = (uint32_t)ballot(live_hi);
+            const uint32_t lm = (uint32_t)(ballot(live) >> hshift); // this half's slots
+            const uint32_t hm = (uint32_t)(ballot(live_hi) >> hshift);
             const uint32_t cnt = (uint32_t)(__popc(lm) + __popc(hm));
             if (cnt) {
                 // entries past the last slot of wu go to the slab after it, which the walk has
@@ -944,12 +951,12 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
                     const uint32_t pos2 = pos + (live ? 1u : 0u); // the high entry's position
                     const uint32_t du2 = (pos2 < kCap) ? wu : T.B + spill;
                     const uint32_t ds2 = (pos2 < kCap) ? pos2 : pos2 - kCap;
-                    if (lane < 32 && live && (du != ru || ds != 2 * slot)) // entries in place stay
+                    if (live && (du != ru || ds != 2 * slot)) // entries in place stay
                         ent[(size_t)du * 64 + ds] = lo;
-                    if (lane < 32 && live_hi && (du2 != ru || ds2 != 2 * slot + 1))
+                    if (live_hi && (du2 != ru || ds2 != 2 * slot + 1))
                         ent[(size_t)du2 * 64 + ds2] = hi;
                 } else {
-                    if (lane < 32 && live && (du != ru || ds != slot)) // pairs in place stay
+                    if (live && (du != ru || ds != slot)) // pairs in place stay
                         T.base[(size_t)du * 32 + ds] = w;
                 }
                 if (ws + cnt > kCap) {
@@ -974,18 +981,18 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
         // 31 becomes all ones: auxiliary half and "no next"); words already so are not written
         uint32_t rest = nxt;
         if (wu != ru)
-            rest = rl((uint32_t)(T.base[(size_t)wu * 32 + slot] >> 32), 31);
+            rest = last_of_half((uint32_t)(T.base[(size_t)wu * 32 + slot] >> 32));
         // the last slab read still holds its own words in w; an earlier tail is rewritten whole
         if constexpr (KO) {
             uint32_t *ent = reinterpret_cast<uint32_t *>(T.base) + (size_t)wu * 64;
             const bool same = wu == ru;
-            if (lane < 32 && 2 * slot >= ws && !(same && (uint32_t)w == kEmpty))
+            if (2 * slot >= ws && !(same && (uint32_t)w == kEmpty))
                 ent[2 * slot] = kEmpty;
-            if (lane < 32 && 2 * slot + 1 >= ws && !(same && (uint32_t)(w >> 32) == kEmpty))
+            if (2 * slot + 1 >= ws && !(same && (uint32_t)(w >> 32) == kEmpty))
                 ent[2 * slot + 1] = kEmpty;
         } else {
             const bool keep = wu == ru && w == kEmptyPair;
-            if (lane < 32 && slot >= ws && !keep)
+            if (slot >= ws && !keep)
                 T.base[(size_t)wu * 32 + slot] = kEmptyPair;
         }
         // the slabs that followed the tail go back to the pool, emptied
@@ -994,10 +1001,9 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
         while (f != kEmpty) {
             if (f >= T.pool_slabs || ++seen > T.pool_slabs)
                 break;
-            const uint32_t nf = rl((uint32_t)(T.pool[(size_t)f * 32 + slot] >> 32), 31);
-            if (lane < 32)
-                T.pool[(size_t)f * 32 + slot] = kEmptyPair;
-            if (lane == 0)
+            const uint32_t nf = last_of_half((uint32_t)(T.pool[(size_t)f * 32 + slot] >> 32));
+            T.pool[(size_t)f * 32 + slot] = kEmptyPair;
+            if (slot == 0)
                 slab_free(T, f);
             f = nf;
         }
@@ -1609,10 +1615,11 @@ sh_status_t sh_flush(sh_table_t *t, uint32_t first_bucket, uint32_t num_buckets,
     if (num_buckets == 0)
         return SH_OK;
     // a light kernel bound by the latency of walking each list: twice the operation kernels'
-    // wavefronts per compute unit
+    // wavefronts per compute unit, two buckets per wavefront
     uint64_t waves = (uint64_t)t->num_cu * 2 * kDefaultWavesPerCU;
-    if (waves > num_buckets)
-        waves = num_buckets;
+    const uint64_t pairs = ((uint64_t)num_buckets + 1) / 2;
+    if (waves > pairs)
+        waves = pairs;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     if (t->v.mode & SH_TABLE_KEYS_ONLY)
         hipLaunchKernelGGL(flush_kernel<true>, dim3(blocks), dim3(kBlock), 0, S(stream), t->v,
