@@ -41,9 +41,14 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
 # Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
 # a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
-TRAFFIC_SRC_SHA = "64b613fbf3b93cd3"
-TRAFFIC_BYTES = {"build": 1355561969, "search_hit": 1039072572, "search_miss": 1039072572,
-                 "mixed": 19375133, "reset": 94022372}
+TRAFFIC_SRC_SHA = "342bf3cb7ca38c26"
+# Per launch, from rocprofv3 TCC_HIT_sum/TCC_MISS_sum and TCC_ATOMIC_sum/TCC_EA0_ATOMIC_sum runs
+# of the same source (profiles/slabhash_step_2p22_l2.md): (L2 hit rate, atomics, atomics that
+# reached memory).
+L2_STATS = {"build": (0.3652, 4795162, 4795162), "search_hit": (0.0941, 0, 0), "search_miss": (0.0941, 0, 0),
+            "mixed": (0.2879, 26724, 26724), "reset": (0.5005, 0, 0)}
+TRAFFIC_BYTES = {"build": 1355594719, "search_hit": 1039101601, "search_miss": 1039101601,
+                 "mixed": 19375764, "reset": 94022372}
 
 
 def source_sha() -> str:
@@ -829,6 +834,14 @@ def main():
         if n_ops:
             kernels[k]["Mops"] = round(n_ops / (avg_ms[k] * 1e-3) / 1e6, 1)
         kernels[k]["traffic_bytes"] = TRAFFIC_BYTES[k] if traffic_ok else None
+        # L2 hit rate and atomics per launch from the same profiled source (else null); the
+        # atomic rate is those atomics over this run's mean duration
+        hit, atomics, to_mem = L2_STATS.get(k, (None, None, None)) if traffic_ok else (None,) * 3
+        kernels[k]["l2_hit_rate"] = hit
+        kernels[k]["atomics_per_launch"] = atomics
+        kernels[k]["atomics_to_memory_per_launch"] = to_mem
+        kernels[k]["atomic_rate_G_per_s"] = (round(atomics / (avg_ms[k] * 1e-3) / 1e9, 2)
+                                             if atomics is not None else None)
     ach = bytes_l[dom] / (avg_ms[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4),
