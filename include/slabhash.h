@@ -235,9 +235,9 @@ sh_status_t sh_stats(sh_table_t *t, sh_stats_t *h_out, void *stream);
    (at most cap entries, in no particular order); *d_count (device uint64) receives the number
    of live pairs even if larger than cap. d_bucket_counts (may be NULL) receives, per bucket,
    three uint32: live, tombstones, slabs. d_violations (device uint32, may be NULL) receives the
-   number of invariant violations found: an empty slot before a full one or in a non-tail
-   slab, a malformed auxiliary word, a next index out of range or not allocated, a chain that
-   does not end. Every output is written by the call (no pre-zeroing needed). */
+   number of invariant violations found: on unique-key tables an empty slot before a full one
+   or in a non-tail slab; on every table a malformed slot or auxiliary word, a next index out of
+   range or not allocated, a chain that does not end. Every output is written by the call (no pre-zeroing needed). */
 sh_status_t sh_dump(sh_table_t *t, uint32_t *d_bucket, uint32_t *d_key, uint32_t *d_val,
                     uint64_t cap, uint32_t *d_bucket_counts, uint64_t *d_count,
                     uint32_t *d_violations, void *stream);
