@@ -812,7 +812,11 @@ def main():
     S.sh_set_launch(h, args.waves_per_cu, 0, 0)
     util = 8.0 * stats_built["live"] / (256.0 * stats_built["slabs_total"])
 
-    # Algorithmic bytes per launch ("Roofline and algorithmic bytes").
+    # Algorithmic bytes per launch: every op reads its inputs and writes its outputs once and
+    # reads the 256-byte slabs its walk visits (v_hit / v_miss per op, from the table's bucket
+    # loads); an insert adds its 8-byte swap and each new slab a 4-byte link and a 4-byte
+    # bitmap word; a mixed batch's updates add one 8-byte swap each; a reset writes the whole
+    # table.
     bytes_l = {
         "build": N_KEYS * (8 + 1 + 8) + 256.0 * v_hit * N_KEYS + new_slabs * (4 + 4),
         "search_hit": N_KEYS * (4 + 4 + 1) + 256.0 * v_hit * N_KEYS,
