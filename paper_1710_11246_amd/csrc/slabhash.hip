@@ -1278,11 +1278,13 @@ sh_status_t check_launch()
 
 // Default launch shape of an operation kind: wavefronts per compute unit and the largest chunk
 // (ops per wavefront). A persistent grid should not exceed the wavefronts that fit at once at
-// the kernel's register use, or the ones that do not fit run after the others. For unique-key
-// pair tables the straight run of loads follows the chunk: inserts and deletes at 16 ops per
-// wavefront use 80 VGPRs (24 wavefronts fit per CU) and ran fastest at 20 per CU (2^22-pair
-// build 254 us against 330 us at 64 ops and 16 per CU); searches ran fastest at 32 ops, 16 per
-// CU (72 VGPRs). The other modes run the full 32-load straight run (about 128 VGPRs: 16 fit).
+// the kernel's register use, or the ones that do not fit run after the others (launch_wpc
+// lowers a default grid to what fits). The straight run of loads follows the chunk: on
+// unique-key pair tables inserts and deletes at 16 ops per wavefront use 78 VGPRs (24
+// wavefronts fit per CU) and ran fastest at 20 per CU (2^22-pair build 254 us against 330 us
+// at 64 ops and 16 per CU); searches ran fastest at 32 ops, 16 per CU (72 VGPRs). Tables with
+// flags take 64-op chunks, halved for small batches like the others, and always run the full
+// 32-load straight run (104 to 132 VGPRs).
 struct Shape {
     uint32_t waves_per_cu, max_ops;
 };
@@ -1322,7 +1324,8 @@ uint32_t ops_per_wave_for(const sh_table *t, uint64_t n, int kind)
 }
 
 // Wavefronts of kernel `fn` that fit on one compute unit at once (its registers and LDS), from
-// the occupancy API, cached per kernel; 64 (no limit) if the query fails.
+// the occupancy API, cached per kernel (one GPU model per process); 64 (no limit) if the query
+// fails, whose error is then cleared so that the launch check after it does not report it.
 uint32_t resident_waves_per_cu(const void *fn)
 {
     static std::mutex mu;
@@ -1335,6 +1338,8 @@ uint32_t resident_waves_per_cu(const void *fn)
     uint32_t w = 64;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) == hipSuccess && nb > 0)
         w = (uint32_t)nb * kWavesPerBlock;
+    else
+        (void)hipGetLastError();
     cache.emplace_back(fn, w);
     return w;
 }
@@ -1381,18 +1386,25 @@ sh_status_t launch_init(sh_table *t, void *stream)
 using OpsFn = void (*)(View, const uint8_t *, const uint32_t *, const uint32_t *, uint64_t,
                       uint32_t *, uint8_t *, uint32_t, uint32_t, uint32_t);
 
+// The operation kernel for kind K at C ops per wavefront, in one table mode: a straight run of
+// C / 2 loads per round, one per op pair.
+template <int K, bool Dup, bool KO>
+OpsFn ops_fn_mode(uint32_t C)
+{
+    return C == 64 ? ops_kernel<K, Dup, KO, 32>
+                   : C == 32 ? ops_kernel<K, Dup, KO, 16>
+                             : C == 16 ? ops_kernel<K, Dup, KO, 8> : ops_kernel<K, Dup, KO, 4>;
+}
+
 // The operation kernel for kind K on table t at C ops per wavefront: unique-key pair tables run
-// a straight run of C / 2 loads per round, the other modes the full 32 (their chunks may still
-// be shorter).
+// a straight run of C / 2 loads per round, tables with flags the full 32 (their chunks may
+// still be shorter).
 template <int K>
 OpsFn ops_fn(const sh_table *t, uint32_t C)
 {
     switch (t->v.mode) {
     case 0:
-        return C == 64 ? ops_kernel<K, false, false, 32>
-                       : C == 32 ? ops_kernel<K, false, false, 16>
-                                 : C == 16 ? ops_kernel<K, false, false, 8>
-                                           : ops_kernel<K, false, false, 4>;
+        return ops_fn_mode<K, false, false>(C);
     case SH_TABLE_DUPLICATES:
         return ops_kernel<K, true, false, 32>;
     case SH_TABLE_KEYS_ONLY:
