@@ -349,7 +349,8 @@ size_t sh_server_scratch_bytes(const sh_server_cfg_t *cfg);
 /* Start serving table t. d_scratch: caller-owned device memory (256-byte aligned, at least
    sh_server_scratch_bytes). Synchronises `stream` once to read the pool occupancy. No other call
    may use the table while the server runs. A table with any flag gives SH_EINVAL (requests run
-   through the batched kernel). */
+   through the batched kernel); SH_EHIP if a HIP call fails, SH_ENOMEM if host memory or the
+   server thread cannot be had (nothing is left running in either case). */
 sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uint8_t *d_ops,
                             const uint32_t *d_keys, const uint32_t *d_vals_in,
                             uint32_t *d_vals_out, uint8_t *d_status, uint64_t n_ops,
@@ -357,8 +358,9 @@ sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uin
                             sh_server_t **out);
 
 /* Admit a request. SH_OK gives a ticket; SH_EBUSY means not admissible now (retry later);
-   SH_ENOMEM means it can never be admitted (its worst case exceeds the pool); SH_EINVAL for a
-   range outside the op arrays or an empty request. */
+   SH_ENOMEM means it can never be admitted (its worst case exceeds the pool) or the server's
+   host records could not grow (nothing was admitted); SH_EINVAL for a range outside the op
+   arrays, an empty request or a stopping server. */
 sh_status_t sh_server_submit(sh_server_t *s, const sh_request_t *req, uint64_t *ticket);
 
 /* *done = 1 once the request's results are in device memory; times on sh_clock_ns's clock.
@@ -371,7 +373,9 @@ sh_status_t sh_server_poll(sh_server_t *s, uint64_t ticket, int *done, uint64_t 
 /* Load driver: submit request i at time t0 + arrival_ns[i] (t0 = the call's start; arrival_ns
    non-decreasing), keeping requests that are not yet admissible in arrival order, until all
    have finished. admit_ns[i] and done_ns[i] (relative to t0) receive the admission and
-   completion times; a request that can never be admitted gets UINT64_MAX in both. */
+   completion times; a request that can never be admitted gets UINT64_MAX in both. SH_EHIP if
+   the server reports a HIP error; SH_ENOMEM if the driver's host bookkeeping cannot be
+   allocated (requests already submitted still run on the server). */
 sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
                              const uint64_t *h_arrival_ns, uint64_t n, uint64_t *h_admit_ns,
                              uint64_t *h_done_ns);

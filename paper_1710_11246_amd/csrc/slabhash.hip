@@ -2340,7 +2340,15 @@ sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uin
     s->base_allocated = (int64_t)stt.pool_allocated;
     s->allocated = s->base_allocated;
     s->base_net = counters_net(s->slots[0].h_cnt);
-    s->thr = std::thread(server_loop, s);
+    try {
+        // a launch takes at most kMaxBatches requests: the server thread never grows these
+        for (uint32_t k = 0; k < s->nslots; ++k)
+            s->slots[k].tickets.reserve(kMaxBatches);
+        s->thr = std::thread(server_loop, s);
+    } catch (...) {
+        server_free(s);
+        return SH_ENOMEM;
+    }
     *out = s;
     return SH_OK;
 }
@@ -2359,8 +2367,6 @@ sh_status_t sh_server_submit(sh_server_t *s, const sh_request_t *req, uint64_t *
         return s->unfinished == 0 ? SH_ENOMEM : SH_EBUSY;
     if (s->unfinished >= s->cfg.max_requests || (int64_t)req->inserts > avail - s->reserved)
         return SH_EBUSY;
-    s->reserved += req->inserts;
-    ++s->unfinished;
     // Finished requests beyond the last kTicketWindow tickets are forgotten once their finish
     // has been reported (their tickets expire), and beyond four windows even if it has not, so
     // a long-running server holds bounded memory.
@@ -2369,14 +2375,28 @@ sh_status_t sh_server_submit(sh_server_t *s, const sh_request_t *req, uint64_t *
         s->reqs.pop_front();
         ++s->reqs_base;
     }
-    s->reqs.emplace_back();
+    // the two containers grow first; if either cannot, the request is refused and nothing
+    // else has changed
+    const uint64_t tk = s->reqs_base + s->reqs.size();
+    try {
+        s->reqs.emplace_back();
+        try {
+            s->pending.push_back(tk);
+        } catch (...) {
+            s->reqs.pop_back();
+            throw;
+        }
+    } catch (...) {
+        return SH_ENOMEM;
+    }
     ServerReq &R = s->reqs.back();
     R.r = *req;
     R.t_admit = clock_now_ns();
     R.t_done = 0;
     R.read = false;
-    *ticket = s->reqs_base + s->reqs.size() - 1;
-    s->pending.push_back(*ticket);
+    s->reserved += req->inserts;
+    ++s->unfinished;
+    *ticket = tk;
     s->cv.notify_one();
     return SH_OK;
 }
@@ -2400,9 +2420,9 @@ sh_status_t sh_server_poll(sh_server_t *s, uint64_t ticket, int *done, uint64_t 
     return s->error.load() ? SH_EHIP : SH_OK;
 }
 
-sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
-                             const uint64_t *h_arrival_ns, uint64_t n, uint64_t *h_admit_ns,
-                             uint64_t *h_done_ns)
+static sh_status_t replay_run(sh_server_t *s, const sh_request_t *h_reqs,
+                              const uint64_t *h_arrival_ns, uint64_t n, uint64_t *h_admit_ns,
+                              uint64_t *h_done_ns)
 {
     if (!s || (n && (!h_reqs || !h_arrival_ns || !h_admit_ns || !h_done_ns)))
         return SH_EINVAL;
@@ -2477,6 +2497,19 @@ sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
             return SH_EHIP;
     }
     return SH_OK;
+}
+
+sh_status_t sh_server_replay(sh_server_t *s, const sh_request_t *h_reqs,
+                             const uint64_t *h_arrival_ns, uint64_t n, uint64_t *h_admit_ns,
+                             uint64_t *h_done_ns)
+{
+    // the driver's bookkeeping grows with n; if it cannot, the call ends with SH_ENOMEM
+    // (requests already submitted still run on the server)
+    try {
+        return replay_run(s, h_reqs, h_arrival_ns, n, h_admit_ns, h_done_ns);
+    } catch (...) {
+        return SH_ENOMEM;
+    }
 }
 
 sh_status_t sh_server_stop(sh_server_t *s)
