@@ -1340,7 +1340,11 @@ uint32_t resident_waves_per_cu(const void *fn)
         w = (uint32_t)nb * kWavesPerBlock;
     else
         (void)hipGetLastError();
-    cache.emplace_back(fn, w);
+    try {
+        cache.emplace_back(fn, w);
+    } catch (...) {
+        // not cached: the next launch asks again
+    }
     return w;
 }
 
@@ -2293,9 +2297,12 @@ sh_status_t sh_server_start(sh_table_t *t, const sh_server_cfg_t *cfg, const uin
         n_ops == 0 || n_ops >= (1ull << 40) || !d_scratch || need == 0 ||
         scratch_bytes < need || (reinterpret_cast<uintptr_t>(d_scratch) & 255u) || t->v.mode)
         return SH_EINVAL;
-    sh_server *s = new (std::nothrow) sh_server();
-    if (!s)
+    sh_server *s = nullptr;
+    try {
+        s = new sh_server(); // its containers may allocate as they are built
+    } catch (...) {
         return SH_ENOMEM;
+    }
     s->t = t;
     s->cfg = c;
     s->ops = d_ops;
