@@ -1323,6 +1323,10 @@ uint32_t ops_per_wave_for(const sh_table *t, uint64_t n, int kind)
     return C;
 }
 
+// The launch sequence number that seeds the allocator's starting blocks; calls on one table may
+// come from several host threads.
+uint32_t next_seq(uint32_t *seq) { return __atomic_fetch_add(seq, 1u, __ATOMIC_RELAXED); }
+
 // Wavefronts of kernel `fn` that fit on one compute unit at once (its registers and LDS), from
 // the occupancy API, cached per kernel (one GPU model per process); 64 (no limit) if the query
 // fails, whose error is then cleared so that the launch check after it does not report it.
@@ -1434,7 +1438,7 @@ sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
     const uint32_t wpc =
         launch_wpc(t->waves_per_cu, default_shape(t, K).waves_per_cu, reinterpret_cast<const void *>(fn));
     const dim3 grid(grid_for(t, n, C, wpc));
-    const uint32_t seq = t->seq++;
+    const uint32_t seq = next_seq(&t->seq);
     hipLaunchKernelGGL(fn, grid, dim3(kBlock), 0, S(stream), t->v, ops, keys, vals, n, vout, sout,
                        seq, C, t->flags);
     return check_launch();
@@ -1581,7 +1585,7 @@ sh_status_t launch_multi(sh_multi *m, const sh_batch_desc_t *d_desc, uint32_t nb
 {
     return launch_multi_raw(m->d_dir, m->T, d_desc, nb, d_ops, d_keys, d_vals_in, d_vals_out,
                             d_status, n_ops, n_ops, m->num_cu, m->waves_per_cu, m->ops_per_wave,
-                            m->seq++, m->flags, stream);
+                            next_seq(&m->seq), m->flags, stream);
 }
 
 } // namespace
@@ -1707,7 +1711,7 @@ sh_status_t sh_alloc_slabs(sh_table_t *t, uint64_t n, uint32_t *d_out, void *str
         return SH_OK;
     const uint64_t blocks = (n + kBlock - 1) / kBlock; // one request per lane
     hipLaunchKernelGGL(alloc_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, S(stream), t->v, n,
-                       d_out, t->seq++);
+                       d_out, next_seq(&t->seq));
     return check_launch();
 }
 
