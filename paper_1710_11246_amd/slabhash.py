@@ -519,15 +519,21 @@ class SlabHash:
 
     @property
     def num_buckets(self) -> int:
+        """Bucket count B."""
         return self.params.num_buckets
 
     def reset(self, stream=None):
+        """Re-initialise the table in place: every slot and next index empty, every pool slab free."""
         sh_reset(self.handle, stream)
 
     def set_launch(self, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0):
+        """Launch shape of later calls (0 = the operation kind's default); `flags` may hold
+        SH_LAUNCH_COUNTERS to accumulate the operation counters `stats()` reports."""
         sh_set_launch(self.handle, waves_per_cu, ops_per_wave, flags)
 
     def launch_shape(self, kind: int, n: int) -> tuple[int, int]:
+        """(waves per CU, ops per wavefront) a call of n ops of `kind` (an SH_OP_* code or
+        SH_KIND_MIXED) would use now."""
         return sh_launch_shape(self.handle, kind, n)
 
     def search_all(self, keys, stream=None):
@@ -560,33 +566,44 @@ class SlabHash:
         sh_flush(self.handle, first, count, stream)
 
     def insert(self, keys, vals=None, stream=None, status=True):
+        """REPLACE each (key, value) pair (INSERT with duplicates; keys alone on a key-only
+        table). Returns the per-op status tensor (1 new, 2 replaced, 0 failed), or None with
+        status=False."""
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
         sh_insert(self.handle, keys, vals, st, stream)
         return st
 
     def build(self, keys, vals=None, stream=None, status=True):
+        """Bulk build: the same operation as `insert`, named after the paper's bulk benchmark."""
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
         sh_build(self.handle, keys, vals, st, stream)
         return st
 
     def delete(self, keys, stream=None):
+        """DELETE each key; returns the per-op status tensor (1 deleted, 0 absent)."""
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
         sh_delete(self.handle, keys, st, stream)
         return st
 
     def search(self, keys, stream=None):
+        """SEARCH each key; returns (values, found) device tensors (value 0xFFFFFFFF when
+        absent; `found` is authoritative)."""
         v = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
         f = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
         sh_search(self.handle, keys, v, f, stream)
         return v, f
 
     def mixed(self, ops, keys, vals, stream=None):
+        """One concurrent batch of SH_OP_SEARCH / SH_OP_INSERT / SH_OP_DELETE ops (uint8);
+        returns (values, status) device tensors. The outcome is linearizable."""
         vo = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
         sh_mixed(self.handle, ops, keys, vals, vo, st, stream)
         return vo, st
 
     def stats(self, stream=None) -> dict:
+        """Walk the table: live and deleted counts, slabs, pool use, error word, invariant
+        violations, hash constants and the operation counters, as a dict. Synchronises."""
         return sh_stats(self.handle, stream)
 
     def dump(self, stream=None):
@@ -634,9 +651,12 @@ class MultiSlabHash:
             self.handle = None
 
     def set_launch(self, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0):
+        """Launch shape of later batched launches (same fields as SlabHash.set_launch)."""
         sh_multi_set_launch(self.handle, waves_per_cu, ops_per_wave, flags)
 
     def mixed(self, desc, nb, ops, keys, vals, stream=None):
+        """One launch over `nb` batches: `desc` holds sh_batch_desc_t records (offset, length,
+        table) into the shared op arrays. Returns (values, status) device tensors."""
         vo = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
         sh_multi_mixed(self.handle, desc, nb, ops, keys, vals, vo, st, stream)
@@ -664,15 +684,22 @@ class Server:
                                       self.status, self.scratch, stream)
 
     def submit(self, offset, length, inserts):
+        """Offer the request for ops [offset, offset + length) with `inserts` inserts among
+        them. Returns (code, ticket): SH_OK with the ticket, SH_EBUSY when it must wait, SH_ENOMEM
+        when it can never fit; other codes raise SlabHashError."""
         return sh_server_submit(self.handle, offset, length, inserts)
 
     def poll(self, ticket):
+        """(done, admit time, done time) of a ticket, in sh_clock_ns nanoseconds."""
         return sh_server_poll(self.handle, ticket)
 
     def replay(self, offsets, lengths, inserts, arrival_ns):
+        """Submit request i (offsets[i], lengths[i], inserts[i]) at arrival_ns[i] after the
+        call's start and wait for all; returns (admit_ns, done_ns) arrays relative to that start."""
         return sh_server_replay(self.handle, offsets, lengths, inserts, arrival_ns)
 
     def stop(self):
+        """Finish admitted work, stop the server thread and free its host resources."""
         if self.handle is not None:
             h, self.handle = self.handle, None
             sh_server_stop(h)
