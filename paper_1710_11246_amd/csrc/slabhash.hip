@@ -1011,15 +1011,15 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
 }
 
 // SEARCHALL and DELETEALL ("Supported Operations"): every live element with the key, in list
-// order, so each op walks its whole list. A wavefront holds a chunk of up to 64 ops, reads
-// their base slabs in one straight run (two ops per load, as in run_chunk), then takes the ops
+// order, so each op walks its whole list. A wavefront holds a chunk of up to 2 NQ ops, reads
+// their base slabs in one straight run of NQ loads (two ops per load, as in run_chunk), then takes the ops
 // a pair at a time: lanes 0..31 walk op 2q's list and lanes 32..63 op 2q+1's, each slab voted
 // on at once. SEARCHALL writes the values of the matching slots in list order from
 // offsets[op], never past `limit` of the op (the next op's offset, or the output's capacity);
 // DELETEALL swaps each matching slot to `gone` (a tombstone, or an empty slot with duplicates),
 // retrying a slot whose value a concurrent replace changed. counts[op] receives the number of
 // matches found (SEARCHALL) or deleted (DELETEALL).
-template <bool Del, bool KO>
+template <bool Del, bool KO, int NQ>
 __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__restrict__ keys,
                                                      uint64_t n, uint32_t *__restrict__ counts,
                                                      const uint64_t *__restrict__ offsets,
@@ -1033,11 +1033,12 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
     const uint32_t wl_ = threadIdx.x >> 6;
     const uint64_t wave = blockIdx.x * (uint64_t)kWavesPerBlock + wl_;
     const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
-    const uint64_t nchunks = (n + 63) / 64;
+    constexpr uint32_t C = 2 * NQ; // ops per chunk, two per load
+    const uint64_t nchunks = (n + C - 1) / C;
     uint32_t *kk = ku[wl_][0], *uu = ku[wl_][1];
     for (uint64_t c = wave; c < nchunks; c += nwaves) {
-        const uint64_t base = c * 64;
-        const uint32_t count = (n - base < 64) ? (uint32_t)(n - base) : 64u;
+        const uint64_t base = c * C;
+        const uint32_t count = (n - base < C) ? (uint32_t)(n - base) : C;
         const bool in = lane < count;
         const uint32_t key = in ? keys[base + lane] : kEmpty;
         const uint64_t res_m = ballot(in && (key == kEmpty || (KO && key == kTombKey)));
@@ -1048,12 +1049,12 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
                        ? bucket_of(key, T.a, T.b, T.B)
                        : 0u;
         __builtin_amdgcn_wave_barrier();
-        uint64_t pre[32];
+        uint64_t pre[NQ];
 #pragma unroll
-        for (int q = 0; q < 32; ++q)
+        for (int q = 0; q < NQ; ++q)
             pre[q] = load_slot<Del>(T.base + (size_t)uu[2 * q + half] * 32 + slot);
 #pragma unroll
-        for (int q = 0; q < 32; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             if (2 * (uint32_t)q >= count)
                 break;
             const uint32_t op = 2 * q + half;
@@ -1422,6 +1423,21 @@ OpsFn ops_fn(const sh_table *t, uint32_t C)
     }
 }
 
+using AllFn = void (*)(View, const uint32_t *, uint64_t, uint32_t *, const uint64_t *,
+                      uint32_t *, uint64_t, uint64_t);
+// SEARCHALL/DELETEALL at C ops per chunk: a straight run of C / 2 loads, one per op pair.
+// 32 ops per chunk by default: 16-load runs at 126 to 130 VGPRs (SEARCHALL) ran 1.6x faster than
+// 32-load runs at 222 to 226 (only 8 wavefronts per CU fit), and DELETEALL 1.25x.
+constexpr uint32_t kAllOps = 32;
+
+template <bool Del, bool KO>
+AllFn all_fn(uint32_t C)
+{
+    return C == 64 ? all_kernel<Del, KO, 32>
+                   : C == 32 ? all_kernel<Del, KO, 16>
+                             : C == 16 ? all_kernel<Del, KO, 8> : all_kernel<Del, KO, 4>;
+}
+
 template <int K>
 sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
                        const uint32_t *vals, uint64_t n, uint32_t *vout, uint8_t *sout,
@@ -1654,20 +1670,20 @@ static sh_status_t launch_all(sh_table *t, bool del, const uint32_t *keys, uint6
                               uint32_t *counts, const uint64_t *offsets, uint32_t *vals,
                               uint64_t cap, void *stream)
 {
-    using AllFn = void (*)(View, const uint32_t *, uint64_t, uint32_t *, const uint64_t *,
-                           uint32_t *, uint64_t, uint64_t);
     const bool dup = (t->v.mode & SH_TABLE_DUPLICATES) != 0;
     const bool ko = (t->v.mode & SH_TABLE_KEYS_ONLY) != 0;
     // what a deleted slot becomes: a tombstone, or with duplicates an empty slot
     const uint64_t gone = ko ? (dup ? kEmpty : kTombKey) : (dup ? kEmptyPair : kTombPair);
-    const AllFn fn = del ? (ko ? all_kernel<true, true> : all_kernel<true, false>)
-                         : (ko ? all_kernel<false, true> : all_kernel<false, false>);
-    // 32-load straight runs, like the full-width operation kernels; the default grid is what
-    // fits at once at these kernels' register use
+    // ops per chunk: the table's setting, else the default; the straight run has one load per
+    // op pair
+    const uint32_t C = t->ops_per_wave ? t->ops_per_wave : kAllOps;
+    const AllFn fn = del ? (ko ? all_fn<true, true>(C) : all_fn<true, false>(C))
+                         : (ko ? all_fn<false, true>(C) : all_fn<false, false>(C));
+    // the default grid is what fits at once at the kernel's register use
     uint64_t waves = (uint64_t)t->num_cu *
                      launch_wpc(t->waves_per_cu, kDefaultWavesPerCU,
                                 reinterpret_cast<const void *>(fn));
-    const uint64_t chunks = (n + 63) / 64;
+    const uint64_t chunks = (n + C - 1) / C;
     if (waves > chunks)
         waves = chunks;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
