@@ -87,11 +87,14 @@ def test_insert_delete_reinsert(oracle_mod, B, domain):
     assert (f.cpu().numpy() == of).all()
 
 
-def test_list_order_across_batches(oracle_mod):
+@pytest.mark.parametrize("opw", [0, 8, 16, 64])
+def test_list_order_across_batches(oracle_mod, opw):
     """Copies inserted one per batch sit in batch order: SEARCH returns the first batch's value
-    and SEARCHALL the values in batch order; DELETE removes the first copy."""
-    say("case: dup list order across batches")
+    and SEARCHALL the values in batch order; DELETE removes the first copy. Run at the default
+    chunk width and at each other one (SEARCHALL and DELETEALL have a kernel per width)."""
+    say("case: dup list order across batches, %d ops per wavefront" % opw)
     t, o, rng = make_dup(oracle_mod, 97, S.pool_slabs_bound(60000), 950)
+    t.set_launch(0, opw)
     keys = W.unique_keys(rng, 15000)
     for r in range(4):
         v = (W.value_of(keys) + np.uint32(r)).astype(np.uint32)
