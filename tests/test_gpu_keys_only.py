@@ -131,11 +131,13 @@ def test_flush(oracle_mod):
     assert_same_table(t, o)
 
 
-def test_multiset_key_only(oracle_mod):
+@pytest.mark.parametrize("opw", [0, 8, 16, 64])
+def test_multiset_key_only(oracle_mod, opw):
     """Duplicates allowed on a key-only table: copies one per batch, deletes with repeats,
-    SEARCHALL counts, DELETEALL, flush."""
-    say("case: key-only with duplicates")
+    SEARCHALL counts, DELETEALL, flush; at the default chunk width and each other one."""
+    say("case: key-only with duplicates, %d ops per wavefront" % opw)
     t, o, rng = make_ko(oracle_mod, 53, S.pool_slabs_bound(100000), 1500, duplicates=True)
+    t.set_launch(0, opw)
     dom = no_tomb_key(W.unique_keys(rng, 4000))
     for r in range(5):
         ks = dom[rng.below(dom.size, 10) < 8]
