@@ -790,8 +790,10 @@ def main():
     avg_ms[dom] = means(ev_timed)[dom]  # the dominant kernel: timed-region events
     per_step_ms[dom] = avg_ms[dom] * (MIX_BATCHES if dom == "mixed" else 1)
 
-    # Structure of the built table (before the mixed batches) for the byte accounting, with
+    # The table as a step leaves it (the next step's reset starts from this), then the
+    # structure of the built table (before the mixed batches) for the byte accounting, with
     # the operation counters switched on for this one build.
+    stats_end = table.stats()
     S.sh_set_launch(h, args.waves_per_cu, 0, S.SH_LAUNCH_COUNTERS)
     S.sh_reset(h, stream)
     S.sh_build(h, keys, vals, st_build, stream)
@@ -815,15 +817,17 @@ def main():
     # Algorithmic bytes per launch: every op reads its inputs and writes its outputs once and
     # reads the 256-byte slabs its walk visits (v_hit / v_miss per op, from the table's bucket
     # loads); an insert adds its 8-byte swap and each new slab a 4-byte link and a 4-byte
-    # bitmap word; a mixed batch's updates add one 8-byte swap each; a reset writes the whole
-    # table.
+    # bitmap word; a mixed batch's updates add one 8-byte swap each; a reset writes the table's
+    # header and base slabs and the pool slabs in use, and reads then zeroes the allocator
+    # bitmaps (a free pool slab is always empty already).
     bytes_l = {
         "build": N_KEYS * (8 + 1 + 8) + 256.0 * v_hit * N_KEYS + new_slabs * (4 + 4),
         "search_hit": N_KEYS * (4 + 4 + 1) + 256.0 * v_hit * N_KEYS,
         "search_miss": N_KEYS * (4 + 4 + 1) + 256.0 * v_miss * N_KEYS,
         "mixed": MIX_BATCH * (1 + 4 + 4 + 4 + 1) + 256.0 * (
             (n_ins + n_miss) * v_miss + (n_del + n_hit) * v_hit) + 8.0 * (n_ins + n_del),
-        "reset": float(table.storage.numel()),
+        "reset": float(4096 + 256 * B + 256 * stats_end["pool_allocated"] +
+                       2 * 256 * (table.params.pool_slabs // 2048)),
     }
     traffic_ok = source_sha() == TRAFFIC_SRC_SHA
     kernels = {}

@@ -129,7 +129,11 @@ size_t sh_storage_bytes(const sh_params_t *p);
 sh_status_t sh_create(const sh_params_t *p, void *d_storage, size_t bytes, void *stream,
                       sh_table_t **out);
 
-/* Re-initialise the table in place (same as the initialisation done by sh_create). */
+/* Re-initialise the table in place: afterwards its storage is byte for byte what sh_create's
+   initialisation writes. Only the header, the base slabs, the pool slabs in use and the bitmaps
+   are written: a free pool slab is always empty (allocation hands slabs out untouched, FLUSH
+   empties the slabs it frees, sh_free_slabs takes empty slabs only). Must not overlap any other
+   call on the table. */
 sh_status_t sh_reset(sh_table_t *t, void *stream);
 
 /* FLUSH ("Flush" subsection) of buckets first_bucket .. first_bucket + num_buckets - 1. In each

@@ -1216,6 +1216,44 @@ __global__ __launch_bounds__(kBlock) void init_kernel(uint4 *store, size_t hdr16
     }
 }
 
+// Re-initialisation of a table in use. A free pool slab is always all ones: allocation hands
+// slabs out untouched, a lost link returns its slab untouched, FLUSH empties the slabs it frees,
+// and slabs given back through sh_free_slabs must be empty. So the storage comes back to what
+// the full initialisation writes by clearing the header, filling the base slabs with ones, and
+// filling only the pool slabs the bitmaps mark allocated before zeroing the bitmaps. Blocks
+// [0, fill_blocks) do the header and base slabs (16-byte stores, grid-stride over them); the
+// other blocks take one bitmap row (2048 pool slabs) per wavefront, grid-stride over the rows.
+__global__ __launch_bounds__(kBlock) void reset_kernel(View T, uint4 *store, size_t hdr16,
+                                                       size_t base16, uint32_t fill_blocks)
+{
+    if (blockIdx.x < fill_blocks) {
+        const size_t total = hdr16 + base16;
+        for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+             i += (size_t)fill_blocks * kBlock) {
+            const uint32_t f = i >= hdr16 ? kEmpty : 0u;
+            store[i] = make_uint4(f, f, f, f);
+        }
+        return;
+    }
+    const uint32_t lane = lane_id();
+    const uint32_t wave = (blockIdx.x - fill_blocks) * kWavesPerBlock + (threadIdx.x >> 6);
+    const uint32_t nwaves = (gridDim.x - fill_blocks) * kWavesPerBlock;
+    uint32_t *pool32 = reinterpret_cast<uint32_t *>(T.pool);
+    for (uint32_t r = wave; r < T.nblk; r += nwaves) {
+        uint32_t word = T.bitmap[(size_t)r * 64 + lane]; // slabs 2048 r + 32 lane + bit
+        // the wavefront writes each allocated slab whole: 64 lanes x 4 bytes
+        for (uint64_t m = ballot(word != 0); m; m = ballot(word != 0)) {
+            const uint32_t j = ffs0(m);
+            const uint32_t bit = (uint32_t)__builtin_ctz(rl(word, j));
+            const size_t slab = (size_t)r * SH_BLOCK_SLABS + j * 32 + bit;
+            pool32[slab * 64 + lane] = kEmpty;
+            if (lane == j)
+                word &= word - 1u; // that slab is done
+        }
+        T.bitmap[(size_t)r * 64 + lane] = 0u;
+    }
+}
+
 } // namespace
 
 // ---------------------------------------------------------------------------------------------
@@ -1641,7 +1679,23 @@ sh_status_t sh_reset(sh_table_t *t, void *stream)
 {
     if (!t)
         return SH_EINVAL;
-    return launch_init(t, stream);
+    Layout L;
+    layout_of(&t->p, &L);
+    const size_t hdr16 = kHeaderBytes / 16;
+    const size_t base16 = (L.pool - L.base) / 16;
+    size_t fill = (hdr16 + base16 + kBlock - 1) / kBlock;
+    const size_t cap = (size_t)t->num_cu * 8;
+    if (fill > cap)
+        fill = cap;
+    // one wavefront per bitmap row, at most the pool's rows
+    const size_t rows = t->v.nblk;
+    size_t pool_blocks = (rows + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (pool_blocks > cap)
+        pool_blocks = cap;
+    hipLaunchKernelGGL(reset_kernel, dim3((uint32_t)(fill + pool_blocks)), dim3(kBlock), 0,
+                       S(stream), t->v, reinterpret_cast<uint4 *>(t->storage), hdr16, base16,
+                       (uint32_t)fill);
+    return check_launch();
 }
 
 sh_status_t sh_flush(sh_table_t *t, uint32_t first_bucket, uint32_t num_buckets, void *stream)

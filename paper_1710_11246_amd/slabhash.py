@@ -523,7 +523,8 @@ class SlabHash:
         return self.params.num_buckets
 
     def reset(self, stream=None):
-        """Re-initialise the table in place: every slot and next index empty, every pool slab free."""
+        """Re-initialise the table in place: every slot and next index empty, every pool slab free
+        (the storage ends byte for byte as a fresh table's)."""
         sh_reset(self.handle, stream)
 
     def set_launch(self, waves_per_cu: int = 0, ops_per_wave: int = 0, flags: int = 0):

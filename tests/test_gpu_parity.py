@@ -159,6 +159,37 @@ def test_launch_shape_reports_the_shape_used():
         t.launch_shape(-1, 10)
 
 
+@pytest.mark.parametrize("dup,ko", [(False, False), (True, False), (False, True)])
+def test_reset_restores_the_initial_storage(oracle_mod, dup, ko):
+    """After inserts, deletes, a FLUSH and slabs taken through the allocator alone, a reset
+    leaves the storage byte for byte as a fresh table's initialisation does, and the table
+    works again."""
+    say("case: reset, duplicates=%s keys_only=%s" % (dup, ko))
+    rng = W.SplitMix64(1401)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    n, B = 50000, 61
+    pool = S.pool_slabs_bound(3 * n)
+    fresh = S.SlabHash(B, pool, a, b, duplicates=dup, keys_only=ko)
+    t = S.SlabHash(B, pool, a, b, duplicates=dup, keys_only=ko)
+    keys = W.unique_keys(rng, n)
+    keys = keys[keys != np.uint32(0xFFFFFFFE)]
+    dev = lambda x: None if ko else S.to_dev(W.value_of(x))
+    t.insert(S.to_dev(keys), dev(keys))
+    t.delete(S.to_dev(keys[::3]))
+    t.flush()
+    t.insert(S.to_dev(keys[::3]), dev(keys[::3]))
+    spare = torch.empty(100, dtype=torch.int32, device="cuda")
+    S.sh_alloc_slabs(t.handle, 100, spare)       # allocated, in no list
+    assert t.stats()["pool_allocated"] > 100
+    t.reset()
+    torch.cuda.synchronize()
+    assert torch.equal(t.storage, fresh.storage)
+    o = oracle_mod.Oracle(B, 62 if ko else M, a, b, duplicates=dup)
+    t.insert(S.to_dev(keys), dev(keys))
+    o.replace(keys, keys if ko else W.value_of(keys))
+    assert_same_table(t, o)
+
+
 def test_empty_calls_are_noops(oracle_mod):
     say("case: empty inputs")
     t, o = make(oracle_mod, 16, 3, 5, 0)
