@@ -104,7 +104,97 @@ def cpu_baseline(wl, batches, B):
     return {"value": round(n_ops / dt / 1e6, 3), "unit": "M ops/s", "cores": 1,
             "kind": "oracle",
             "sample": "one full step on one host core: build 2^22, 2^22 hit + 2^22 miss "
-                      "searches, 16 mixed batches of 2^16 (%.1f s)" % dt}
+                      "searches, 16 mixed batches of 2^16 (%.1f s)" % dt,
+            "host": host_info()}
+
+
+def host_info() -> dict:
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)), "cpu": cpu}
+
+
+def host_threads(cap: int = 16) -> int:
+    """Threads for the host-side runs: the CPUs this process may use, at most `cap`."""
+    return max(1, min(cap, len(os.sched_getaffinity(0))))
+
+
+def oracle_partitioned(B, hash_a, hash_b, build, searches, batches, threads):
+    """One step's ops on `threads` oracles at once. Thread i owns the buckets h(k) mod threads
+    and applies its share of every phase in the original order, so each bucket sees the same
+    sequence of ops as under the single-threaded oracle, and every per-op result is the same
+    (ops on different buckets commute). The oracle's C calls release the interpreter lock.
+
+    build: (keys, vals); searches: list of key arrays; batches: list of (ops, keys, vals).
+    Returns (build status, [(vals, found) per search], [(vals, status) per batch], oracles)."""
+    import threading
+    import oracle
+    from paper_1710_11246_amd import slabhash as S
+    T = int(threads)
+    orcs = [None] * T
+    orcs[0] = oracle.Oracle(B, S.SH_SLAB_PAIRS, hash_a, hash_b)
+
+    def split(keys):
+        part = orcs[0].bucket_of(keys) % np.uint32(T)
+        return [np.flatnonzero(part == i) for i in range(T)]
+
+    bk, bv = build
+    b_idx = split(bk)
+    s_idx = [split(q) for q in searches]
+    m_idx = [split(k) for _, k, _ in batches]
+    st_build = np.empty(bk.size, np.uint8)
+    s_out = [(np.empty(q.size, np.uint32), np.empty(q.size, np.uint8)) for q in searches]
+    m_out = [(np.empty(k.size, np.uint32), np.empty(k.size, np.uint8)) for _, k, _ in batches]
+    errors = []
+
+    def work(i):
+        try:
+            if orcs[i] is None:
+                orcs[i] = oracle.Oracle(B, S.SH_SLAB_PAIRS, hash_a, hash_b)
+            o = orcs[i]
+            ix = b_idx[i]
+            st_build[ix] = o.replace(bk[ix], bv[ix])
+            for q, idx, (vo, fo) in zip(searches, s_idx, s_out):
+                ix = idx[i]
+                v, f, _ = o.search(q[ix])
+                vo[ix], fo[ix] = v, f
+            for (ops, k, v), idx, (vo, so) in zip(batches, m_idx, m_out):
+                ix = idx[i]
+                vo[ix], so[ix] = o.mixed(ops[ix], k[ix], v[ix])
+        except Exception as e:  # re-raised in the caller
+            errors.append(e)
+
+    ths = [threading.Thread(target=work, args=(i,)) for i in range(T)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    if errors:
+        raise errors[0]
+    return st_build, s_out, m_out, orcs
+
+
+def cpu_partitioned(wl, batches, B):
+    """The CPU oracle over one whole step, bucket-partitioned across the host's cores."""
+    T = host_threads()
+    t0 = time.perf_counter()
+    oracle_partitioned(B, wl.hash_a, wl.hash_b, (wl["keys"], wl["vals"]),
+                       [wl["q_hit"], wl["q_miss"]], batches, T)
+    dt = time.perf_counter() - t0
+    n_ops = 3 * N_KEYS + MIX_BATCHES * MIX_BATCH
+    return {"value": round(n_ops / dt / 1e6, 3), "unit": "M ops/s", "cores": T,
+            "kind": "oracle, bucket-partitioned",
+            "sample": "one full step on %d host threads, ops routed to thread h(k) mod %d in "
+                      "their original order (%.2f s, routing and table set-up included)"
+                      % (T, T, dt),
+            "host": host_info()}
 
 
 def run_batched(seed: int = 31, T: int = 256, rounds: int = 20, wpc_override: int = 0):
@@ -947,10 +1037,12 @@ def main():
         log("served form")
         served = run_served()
 
-    cpu = None
+    cpu = cpu_part = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(wl, batches, B)
+        log("cpu baseline (oracle, bucket-partitioned)")
+        cpu_part = cpu_partitioned(wl, batches, B)
 
     out = {
         "metric": "M ops/s build/search/mixed at 2^22 keys vs HBM peak",
@@ -983,6 +1075,7 @@ def main():
         "duplicates": duplicates,
         "keys_only": keys_only,
         "cpu_baseline": cpu,
+        "cpu_partitioned": cpu_part,
     }
     if sweep is not None:
         out["sweep"] = sweep
