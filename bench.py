@@ -473,6 +473,61 @@ def run_served(seed: int = 41, n_keys: int = 1 << 26, n_req: int = 10000,
     }
 
 
+def sweep_utilisation(wl0, n_seeds: int = 5, reps: int = 3) -> dict:
+    """Bulk build of 2^22 keys, then 2^22 all-hit and 2^22 all-miss searches, at every
+    utilisation target's bucket count, for `n_seeds` independent workloads (the first is the
+    step's). Per seed: the median of `reps` runs after one untimed run; reported: the median
+    over seeds in M ops/s, the range over seeds, and the achieved utilisation's range."""
+    import torch
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    dev = "cuda"
+    st = torch.empty(N_KEYS, dtype=torch.uint8, device=dev)
+    v_out = torch.empty(N_KEYS, dtype=torch.int32, device=dev)
+    f_out = torch.empty(N_KEYS, dtype=torch.uint8, device=dev)
+    names = ["build", "search_hit", "search_miss"]
+    per = {u: {"util": [], **{nm: [] for nm in names}} for u in B_FOR_UTIL}
+    for si in range(n_seeds):
+        wl = wl0 if si == 0 else W.bulk(seed=1000 + si, n=N_KEYS, prime=S.SH_HASH_PRIME)
+        log("utilisation sweep: seed %d of %d" % (si + 1, n_seeds))
+        keys, vals = S.to_dev(wl["keys"]), S.to_dev(wl["vals"])
+        q_hit, q_miss = S.to_dev(wl["q_hit"]), S.to_dev(wl["q_miss"])
+        for u, Bu in sorted(B_FOR_UTIL.items()):
+            tu = S.SlabHash(Bu, S.pool_slabs_bound(N_KEYS), wl.hash_a, wl.hash_b)
+            res = {nm: [] for nm in names}
+            for rep in range(reps + 1):
+                tu.reset()
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                e[0].record()
+                S.sh_build(tu.handle, keys, vals, st)
+                e[1].record()
+                S.sh_search(tu.handle, q_hit, v_out, f_out)
+                e[2].record()
+                S.sh_search(tu.handle, q_miss, v_out, f_out)
+                e[3].record()
+                torch.cuda.synchronize()
+                if rep:
+                    for i, nm in enumerate(names):
+                        res[nm].append(e[i].elapsed_time(e[i + 1]))
+            assert bool((st == 1).all()) and bool((f_out == 0).all())
+            s_u = tu.stats()
+            per[u]["util"].append(8.0 * s_u["live"] / (256.0 * s_u["slabs_total"]))
+            for nm in names:
+                per[u][nm].append(N_KEYS / (float(np.median(res[nm])) * 1e-3) / 1e6)
+            del tu
+        del keys, vals, q_hit, q_miss
+    out = {"seeds": n_seeds, "reps_per_seed": reps}
+    for u, Bu in sorted(B_FOR_UTIL.items()):
+        r = {"num_buckets": Bu,
+             "utilisation": [round(min(per[u]["util"]), 4), round(max(per[u]["util"]), 4)]}
+        for nm in names:
+            xs = per[u][nm]
+            r[nm] = round(float(np.median(xs)), 1)
+            r[nm + "_range"] = [round(min(xs), 1), round(max(xs), 1)]
+        out[str(u)] = r
+    return out
+
+
 def sweep_sizes(log2_sizes=(16, 18, 20, 22, 24, 26), util: float = 0.6, reps: int = 5) -> dict:
     """Bulk build, all-hit search and all-miss search against table size ("Bulk benchmarks"): n
     distinct uniform keys for each n = 2^k, buckets from the Binomial model for the target
@@ -786,6 +841,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="also time build/search at every utilisation target")
+    ap.add_argument("--sweep-seeds", type=int, default=5,
+                    help="independent workloads of the utilisation sweep")
     ap.add_argument("--sweep-sizes", action="store_true",
                     help="also time build/search for table sizes 2^16 .. 2^26 at utilisation 0.6")
     ap.add_argument("--sweep-batches", action="store_true",
@@ -984,30 +1041,7 @@ def main():
 
     sweep = None
     if args.sweep:
-        sweep = {}
-        for u, Bu in sorted(B_FOR_UTIL.items()):
-            tu = S.SlabHash(Bu, S.pool_slabs_bound(N_KEYS), wl.hash_a, wl.hash_b)
-            res = {}
-            for rep in range(4):
-                tu.reset()
-                e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-                e[0].record()
-                S.sh_build(tu.handle, keys, vals, st_build)
-                e[1].record()
-                S.sh_search(tu.handle, q_hit, v_out, f_out)
-                e[2].record()
-                S.sh_search(tu.handle, q_miss, v_out, f_out)
-                e[3].record()
-                torch.cuda.synchronize()
-                if rep:
-                    for i, nm in enumerate(["build", "search_hit", "search_miss"]):
-                        res.setdefault(nm, []).append(e[i].elapsed_time(e[i + 1]))
-            s_u = tu.stats()
-            sweep[str(u)] = {"num_buckets": Bu,
-                             "utilisation": round(8.0 * s_u["live"] / (256.0 * s_u["slabs_total"]), 4),
-                             **{nm: round(N_KEYS / (float(np.median(v)) * 1e-3) / 1e6, 1)
-                                for nm, v in res.items()}}
-            del tu
+        sweep = sweep_utilisation(wl, args.sweep_seeds)
 
     sizes = None
     if args.sweep_sizes:
