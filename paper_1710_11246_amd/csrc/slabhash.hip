@@ -1223,12 +1223,15 @@ __global__ __launch_bounds__(kBlock) void init_kernel(uint4 *store, size_t hdr16
 // filling only the pool slabs the bitmaps mark allocated before zeroing the bitmaps. Blocks
 // [0, fill_blocks) do the header and base slabs (16-byte stores, grid-stride over them); the
 // other blocks take one bitmap row (2048 pool slabs) per wavefront, grid-stride over the rows.
+// The bitmap walkers take the first blocks, so they are dispatched before the fill blocks
+// occupy the CUs; their dependent bitmap loads then overlap the fill instead of trailing it.
 __global__ __launch_bounds__(kBlock) void reset_kernel(View T, uint4 *store, size_t hdr16,
-                                                       size_t base16, uint32_t fill_blocks)
+                                                       size_t base16, uint32_t pool_blocks)
 {
-    if (blockIdx.x < fill_blocks) {
+    if (blockIdx.x >= pool_blocks) {
         const size_t total = hdr16 + base16;
-        for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+        const uint32_t fill_blocks = gridDim.x - pool_blocks;
+        for (size_t i = (size_t)(blockIdx.x - pool_blocks) * kBlock + threadIdx.x; i < total;
              i += (size_t)fill_blocks * kBlock) {
             const uint32_t f = i >= hdr16 ? kEmpty : 0u;
             store[i] = make_uint4(f, f, f, f);
@@ -1236,8 +1239,8 @@ __global__ __launch_bounds__(kBlock) void reset_kernel(View T, uint4 *store, siz
         return;
     }
     const uint32_t lane = lane_id();
-    const uint32_t wave = (blockIdx.x - fill_blocks) * kWavesPerBlock + (threadIdx.x >> 6);
-    const uint32_t nwaves = (gridDim.x - fill_blocks) * kWavesPerBlock;
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const uint32_t nwaves = pool_blocks * kWavesPerBlock;
     uint32_t *pool32 = reinterpret_cast<uint32_t *>(T.pool);
     for (uint32_t r = wave; r < T.nblk; r += nwaves) {
         uint32_t word = T.bitmap[(size_t)r * 64 + lane]; // slabs 2048 r + 32 lane + bit
@@ -1694,7 +1697,7 @@ sh_status_t sh_reset(sh_table_t *t, void *stream)
         pool_blocks = cap;
     hipLaunchKernelGGL(reset_kernel, dim3((uint32_t)(fill + pool_blocks)), dim3(kBlock), 0,
                        S(stream), t->v, reinterpret_cast<uint4 *>(t->storage), hdr16, base16,
-                       (uint32_t)fill);
+                       (uint32_t)pool_blocks);
     return check_launch();
 }
 
