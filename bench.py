@@ -41,14 +41,14 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
 # Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
 # a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
-TRAFFIC_SRC_SHA = "3b6adc3494545600"
+TRAFFIC_SRC_SHA = "02295a463c8ca04f"
 # Per launch, from rocprofv3 TCC_HIT_sum/TCC_MISS_sum and TCC_ATOMIC_sum/TCC_EA0_ATOMIC_sum runs
 # of the same source (profiles/slabhash_step_2p22_l2.md): (L2 hit rate, atomics, atomics that
 # reached memory).
-L2_STATS = {"build": (0.3652, 4795561, 4795561), "search_hit": (0.0943, 0, 0), "search_miss": (0.0943, 0, 0),
-            "mixed": (0.2802, 26739, 26739), "reset": (0.5032, 0, 0)}
-TRAFFIC_BYTES = {"build": 1355677966, "search_hit": 1039119136, "search_miss": 1039119136,
-                 "mixed": 19364941, "reset": 55896690}
+L2_STATS = {"build": (0.3643, 4796460, 4796460), "search_hit": (0.0943, 0, 0), "search_miss": (0.0943, 0, 0),
+            "mixed": (0.2812, 26740, 26740), "reset": (0.5032, 0, 0)}
+TRAFFIC_BYTES = {"build": 1355416374, "search_hit": 1039118007, "search_miss": 1039118007,
+                 "mixed": 19357748, "reset": 55896689}
 
 
 def source_sha() -> str:

@@ -326,6 +326,8 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
 {
     constexpr bool kCoherent = (K != kSearch);
     constexpr bool kHasIns = (K == kInsert || K == kMixed);
+    // unique-key pair inserts write their pair into a new tail slab before linking it
+    constexpr bool kPrefill = !Dup && !KO;
     const uint32_t lane = lane_id();
     const uint32_t half = lane >> 5, slot = lane & 31;
     const bool is31 = slot == 31;
@@ -583,16 +585,44 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
                 }
                 ++cnt.allocs;
                 uint32_t *link = reinterpret_cast<uint32_t *>(tail + 31) + 1;
-                uint32_t old = 0;
-                if (lane == 0)
-                    old = cas32(link, kEmpty, idx);
+                // Unique-key pair inserts put their pair in slot 0 of the new slab before linking
+                // it: the slab is private (and empty) until linked, so a winning link publishes
+                // the pair and the op is done in this round. Swaps are performed in memory; the
+                // link's new index passes through the prefill's result, so the link is issued
+                // only once the pair is in place, and no reader can follow it and miss the pair.
+                uint64_t *fresh = T.base + (size_t)(T.B + idx) * 32;
+                const uint64_t pair = ((uint64_t)rl(val, j) << 32) | rl(key, j);
+                uint32_t old = 0, put = 0;
+                if (lane == 0) {
+                    uint32_t desired = idx;
+                    if constexpr (kPrefill) {
+                        put = cas64(fresh, kEmptyPair, pair) == kEmptyPair;
+                        asm volatile("" : "+v"(desired) : "v"(put));
+                    }
+                    old = cas32(link, kEmpty, desired);
+                }
                 old = rl(old, 0);
+                put = rl(put, 0);
                 if (old == kEmpty) {
-                    loc = wl(loc, j, idx);
+                    if (put) {
+                        if (lane == j)
+                            rs = 1u; // a new key, in slot 0 of the new tail
+                        todo &= ~(1ull << j);
+                    } else {
+                        loc = wl(loc, j, idx);
+                    }
                 } else {
                     ++cnt.link_lost;
-                    if (lane == 0)
-                        slab_free(T, idx); // another wavefront linked first
+                    if (lane == 0) {
+                        // another wavefront linked first; a free slab must be empty, so the
+                        // pair is taken out before the slab is returned
+                        uint32_t freed = idx;
+                        if (put) {
+                            const uint32_t back = cas64(fresh, pair, kEmptyPair) == pair;
+                            asm volatile("" : "+v"(freed) : "v"(back));
+                        }
+                        slab_free(T, freed);
+                    }
                     loc = wl(loc, j, old);
                 }
             }
