@@ -131,7 +131,8 @@ sh_status_t sh_create(const sh_params_t *p, void *d_storage, size_t bytes, void 
 
 /* Re-initialise the table in place: afterwards its storage is byte for byte what sh_create's
    initialisation writes. Only the header, the base slabs, the pool slabs in use and the bitmaps
-   are written: a free pool slab is always empty (allocation hands slabs out untouched, FLUSH
+   are written: a free pool slab is always empty (allocation hands slabs out untouched, an
+   insert that loses the link of its new slab takes its pair out again before freeing it, FLUSH
    empties the slabs it frees, sh_free_slabs takes empty slabs only). Must not overlap any other
    call on the table. */
 sh_status_t sh_reset(sh_table_t *t, void *stream);
@@ -185,7 +186,7 @@ sh_status_t sh_launch_shape(const sh_table_t *t, int kind, uint64_t n, uint32_t 
 /* Bulk build: insert n pairs, each lane of a wavefront holding one ("Bulk benchmarks"; the
    paper notes a bulk build and an incremental batch insertion are the same operation). Uses
    REPLACE semantics ("Supported Operations": replace the value of an existing key, else insert
-   at the first empty slot, linking a new slab when the tail is full); on a table with
+   at the first empty slot, else in slot 0 of a new slab linked when the tail is full); on a table with
    SH_TABLE_DUPLICATES, INSERT semantics (the first empty slot from the head, status always 1
    unless the pool is exhausted). d_status may be NULL. */
 sh_status_t sh_build(sh_table_t *t, const uint32_t *d_keys, const uint32_t *d_vals, uint64_t n,
