@@ -351,3 +351,35 @@ def test_mixed_with_repeated_keys_linearizable(oracle_mod):
         # continue from the GPU's state: rebuild the oracle from its dump
         o = oracle_mod.Oracle(7, M, a, b)
         o.replace(tk, tv)
+
+
+def test_lost_links_leave_free_slabs_empty(oracle_mod):
+    """Many wavefronts growing the same four lists at once lose link races; each loser has
+    already put its pair into slot 0 of its new slab, and must take it out before freeing the
+    slab. Every pool slab the bitmaps mark free must then be all ones, as the reset and the
+    allocator assume, and the table must equal the oracle's."""
+    say("case: lost links, B=4, n=100000")
+    rng = W.SplitMix64(1501)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    n, B = 100000, 4
+    pool = S.pool_slabs_bound(n)
+    t = S.SlabHash(B, pool, a, b)
+    o = oracle_mod.Oracle(B, M, a, b)
+    S.sh_set_launch(t.handle, 0, 0, S.SH_LAUNCH_COUNTERS)
+    keys = W.unique_keys(rng, n)
+    st = t.insert(S.to_dev(keys), S.to_dev(W.value_of(keys)))
+    assert (st.cpu().numpy() == o.replace(keys, W.value_of(keys))).all()
+    stats = assert_same_table(t, o)
+    assert stats["link_lost"] > 0, "no link race happened; the case tests nothing"
+    torch.cuda.synchronize()
+    raw = t.storage.view(torch.uint8).cpu().numpy()
+    base = 4096
+    pool_at = base + B * 256
+    bitmap_at = pool_at + pool * 256
+    words = raw[bitmap_at:bitmap_at + (pool // 2048) * 256].view(np.uint32)
+    # slab 2048 r + 32 w + bit is marked by bit `bit` of word 64 r + w
+    allocated = ((words[:, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(-1).astype(bool)
+    assert int(allocated.sum()) == stats["pool_allocated"]
+    slabs = raw[pool_at:bitmap_at].reshape(pool, 256)
+    free_dirty = np.flatnonzero(~allocated & (slabs != 0xFF).any(axis=1))
+    assert free_dirty.size == 0, "free pool slabs holding data: %s" % free_dirty[:8]
