@@ -156,14 +156,13 @@ def oracle_partitioned(B, hash_a, hash_b, build, searches, batches, threads):
     orcs = [None] * T
     orcs[0] = oracle.Oracle(B, S.SH_SLAB_PAIRS, hash_a, hash_b)
 
-    def split(keys):
-        part = orcs[0].bucket_of(keys) % np.uint32(T)
-        return [np.flatnonzero(part == i) for i in range(T)]
+    def part_of(keys):  # the thread each op goes to
+        return (orcs[0].bucket_of(keys) % np.uint32(T)).astype(np.uint8)
 
     bk, bv = build
-    b_idx = split(bk)
-    s_idx = [split(q) for q in searches]
-    m_idx = [split(k) for _, k, _ in batches]
+    b_part = part_of(bk)
+    s_part = [part_of(q) for q in searches]
+    m_part = [part_of(k) for _, k, _ in batches]
     st_build = np.empty(bk.size, np.uint8)
     s_out = [(np.empty(q.size, np.uint32), np.empty(q.size, np.uint8)) for q in searches]
     m_out = [(np.empty(k.size, np.uint32), np.empty(k.size, np.uint8)) for _, k, _ in batches]
@@ -174,14 +173,16 @@ def oracle_partitioned(B, hash_a, hash_b, build, searches, batches, threads):
             if orcs[i] is None:
                 orcs[i] = oracle.Oracle(B, S.SH_SLAB_PAIRS, hash_a, hash_b)
             o = orcs[i]
-            ix = b_idx[i]
+            # each thread finds its own share, in the original order (numpy's compare and
+            # nonzero release the interpreter lock, so the routing runs in parallel too)
+            ix = np.flatnonzero(b_part == i)
             st_build[ix] = o.replace(bk[ix], bv[ix])
-            for q, idx, (vo, fo) in zip(searches, s_idx, s_out):
-                ix = idx[i]
+            for q, part, (vo, fo) in zip(searches, s_part, s_out):
+                ix = np.flatnonzero(part == i)
                 v, f, _ = o.search(q[ix])
                 vo[ix], fo[ix] = v, f
-            for (ops, k, v), idx, (vo, so) in zip(batches, m_idx, m_out):
-                ix = idx[i]
+            for (ops, k, v), part, (vo, so) in zip(batches, m_part, m_out):
+                ix = np.flatnonzero(part == i)
                 vo[ix], so[ix] = o.mixed(ops[ix], k[ix], v[ix])
         except Exception as e:  # re-raised in the caller
             errors.append(e)
