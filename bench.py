@@ -202,7 +202,7 @@ def cpu_partitioned(wl, batches, B):
     T = host_threads()
     runs, dt = repeat_for(lambda: oracle_partitioned(
         B, wl.hash_a, wl.hash_b, (wl["keys"], wl["vals"]), [wl["q_hit"], wl["q_miss"]],
-        batches, T))
+        batches, T), max_runs=100)
     n_ops = 3 * N_KEYS + MIX_BATCHES * MIX_BATCH
     return {"value": round(runs * n_ops / dt / 1e6, 3), "unit": "M ops/s", "cores": T,
             "kind": "oracle, bucket-partitioned",
