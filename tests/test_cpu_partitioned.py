@@ -72,3 +72,12 @@ def test_host_threads_bounded():
     assert bench.host_threads(cap=1) == 1
     info = bench.host_info()
     assert info["nproc"] >= info["usable_cpus"] >= 1
+
+
+def test_repeat_for_bounds():
+    calls = []
+    runs, dt = bench.repeat_for(lambda: calls.append(1), min_s=0.0, max_runs=5)
+    assert runs == 1 and len(calls) == 1          # one run always happens
+    calls.clear()
+    runs, dt = bench.repeat_for(lambda: calls.append(1), min_s=3600.0, max_runs=7)
+    assert runs == 7 and len(calls) == 7 and dt < 3600.0   # the cap ends a long sample
