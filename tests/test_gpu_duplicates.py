@@ -13,6 +13,7 @@ import torch
 from paper_1710_11246_amd import slabhash as S
 from paper_1710_11246_amd import workload as W
 
+import host_walk as HW
 from test_gpu_parity import M, assert_same_table
 
 pytestmark = pytest.mark.gpu
@@ -125,13 +126,20 @@ def test_list_order_across_batches(oracle_mod, opw):
 
 
 def test_mixed_batch_with_duplicates(oracle_mod):
-    """Inserts, deletes and searches on disjoint key roles in one concurrent batch."""
+    """Inserts, deletes and searches on disjoint key roles in one concurrent batch. The storage
+    is checked on the host (host_walk) after the base build and after the batch, before any
+    bound, so a failure names the first invariant broken: a slab in two lists, a slab in a list
+    but free, an allocated slab in no list, a free slab that is not empty, or allocator bits
+    that differ from the lists' slabs."""
     say("case: dup mixed batch")
     t, o, rng = make_dup(oracle_mod, 211, S.pool_slabs_bound(80000), 960)
     base = W.unique_keys(rng, 20000)
     bv = W.value_of(base)
-    t.insert(S.to_dev(base), S.to_dev(bv))
+    assert bool((t.insert(S.to_dev(base), S.to_dev(bv)) == 1).all())
     o.replace(base, bv)
+    _, _, slabs0 = HW.check_structure(t)
+    _, _, o_slabs0 = o.bucket_stats()
+    assert (slabs0 == o_slabs0).all(), "the base build linked a slab beyond its inserts"
     ins = base[rng.below(6000, 5000)]                      # more copies of some keys
     dels = base[5000 + rng.permutation(5000)[:3000]]        # keys with one copy
     srch = base[10000:20000][rng.below(8000, 10000)]        # untouched single copies
@@ -143,22 +151,37 @@ def test_mixed_batch_with_duplicates(oracle_mod):
     ops, k, v = ops[perm], k[perm], v[perm]
     gv, gs = t.mixed(S.to_dev(ops), S.to_dev(k), S.to_dev(v))
     ov, ost = o.mixed(ops, k, v)
+    h_live, h_tomb, h_slabs = HW.check_structure(t)
     assert (gs.cpu().numpy() == ost).all() and (S.to_host_u32(gv) == ov).all()
-    # An insert that read its slab before a concurrent delete emptied a slot appends instead of
-    # filling it (the insert linearises first), so a bucket's slab count lies between the
-    # oracle's in batch order and the oracle's with every insert ahead of every delete.
     st = assert_same_table(t, o, check_counts=False)
-    o2 = oracle_mod.Oracle(211, M, o.a, o.b, duplicates=True)
-    o2.replace(base, bv)
-    ins_m = ops == W.OP_INSERT
-    o2.replace(k[ins_m], v[ins_m])
-    o2.delete(k[ops == W.OP_DELETE])
     _, _, _, counts, _ = t.dump()
-    live, tomb, lo_slabs = o.bucket_stats()
-    _, _, hi_slabs = o2.bucket_stats()
+    # the library's walk agrees with the host's reading of the storage
+    assert (counts[:, 0] == h_live).all() and (counts[:, 1] == h_tomb).all()
+    assert (counts[:, 2] == h_slabs).all()
+    assert st["pool_allocated"] == int((h_slabs - 1).sum())
+    live, tomb, _ = o.bucket_stats()
     assert (counts[:, 0] == live).all() and (counts[:, 1] == 0).all()
-    assert (lo_slabs <= counts[:, 2]).all() and (counts[:, 2] <= hi_slabs).all()
-    assert st["pool_allocated"] == int((counts[:, 2].astype(np.int64) - 1).sum())
+    # An insert that read its slab before a concurrent delete emptied a slot appends instead
+    # of filling it (the insert linearises first). So a bucket's slab count lies between the
+    # oracle's with every delete ahead of every insert (most holes refilled) and the oracle's
+    # with every insert ahead of every delete (no hole refilled).
+    ins_m, del_m = ops == W.OP_INSERT, ops == W.OP_DELETE
+    o_lo = oracle_mod.Oracle(211, M, o.a, o.b, duplicates=True)
+    o_lo.replace(base, bv)
+    o_lo.delete(k[del_m])
+    o_lo.replace(k[ins_m], v[ins_m])
+    o_hi = oracle_mod.Oracle(211, M, o.a, o.b, duplicates=True)
+    o_hi.replace(base, bv)
+    o_hi.replace(k[ins_m], v[ins_m])
+    o_hi.delete(k[del_m])
+    _, _, lo_slabs = o_lo.bucket_stats()
+    _, _, hi_slabs = o_hi.bucket_stats()
+    over = np.flatnonzero(counts[:, 2] > hi_slabs)
+    assert over.size == 0, "bucket %d: %d slabs, inserts-first bound %d" % (
+        int(over[0]), int(counts[over[0], 2]), int(hi_slabs[over[0]]))
+    under = np.flatnonzero(counts[:, 2] < lo_slabs)
+    assert under.size == 0, "bucket %d: %d slabs, deletes-first bound %d" % (
+        int(under[0]), int(counts[under[0], 2]), int(lo_slabs[under[0]]))
 
 
 def test_flush_drops_empty_slots(oracle_mod):

@@ -10,6 +10,7 @@ import torch
 from paper_1710_11246_amd import slabhash as S
 from paper_1710_11246_amd import workload as W
 
+import host_walk as HW
 import linearize as LZ
 
 pytestmark = pytest.mark.gpu
@@ -37,6 +38,13 @@ def make(oracle_mod, B, a, b, pool):
 
 def assert_same_table(t, o, check_counts=True):
     b, k, v, counts, viol = t.dump()
+    if getattr(t, "storage", None) is not None:
+        # the raw storage read on the host: lists, allocator bits and free slabs, and the
+        # library walk's per-bucket counts against it
+        ko = bool(t.params.flags & S.SH_TABLE_KEYS_ONLY)
+        h_live, h_tomb, h_slabs = HW.check_structure(t, keys_only=ko)
+        assert (counts[:, 0] == h_live).all() and (counts[:, 1] == h_tomb).all()
+        assert (counts[:, 2] == h_slabs).all()
     assert viol == 0, "structure invariant violated"
     ob, ok, ov = o.dump()
     order = np.lexsort((ov, ok, ob))  # the live multiset: equal keys may sit in any order
