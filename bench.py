@@ -69,6 +69,35 @@ def chain_visits(occ: np.ndarray, m: int = 31) -> float:
     return float((m * full * (full + 1) // 2 + rem * (full + 1)).sum())
 
 
+def op_bytes(kind: str, n: int, v_hit: float, v_miss: float, new_slabs: int = 0,
+             mix=None) -> float:
+    """Algorithmic bytes of one launch of n ops, with v_hit / v_miss the mean slabs a walk to a
+    present key / to the end of a list reads (256 bytes each):
+      search:  4 (key) + 256 v + 4 (value) + 1 (found);
+      insert:  8 (pair) + 256 v_miss (the whole list is read to rule the key out) + 64 (the
+               written sector of the swapped slot) + 1 (status), plus 8 per new slab (its
+               bitmap word and the link), counted exactly when known;
+      delete:  4 + 256 v_hit + 64 + 1;
+      mixed:   per op 1 (op) + 4 (key) + 4 (value in) + 4 (value out) + 1 (status); slabs
+               v_miss for inserts and absent searches, v_hit for deletes and present searches;
+               64 per insert or delete; 8 / 31 per insert for new slabs (amortised).
+    mix = (inserts, deletes, present searches, absent searches) of a mixed batch."""
+    if kind == "search_hit":
+        return n * (4 + 4 + 1) + 256.0 * v_hit * n
+    if kind == "search_miss":
+        return n * (4 + 4 + 1) + 256.0 * v_miss * n
+    if kind == "insert":
+        return n * (8 + 64 + 1) + 256.0 * v_miss * n + 8.0 * new_slabs
+    if kind == "delete":
+        return n * (4 + 64 + 1) + 256.0 * v_hit * n
+    if kind == "mixed":
+        ni, nd, nh, nm = mix
+        assert ni + nd + nh + nm == n
+        return (n * (1 + 4 + 4 + 4 + 1) + 256.0 * ((ni + nm) * v_miss + (nd + nh) * v_hit)
+                + 64.0 * (ni + nd) + 8.0 * ni / 31)
+    raise ValueError(kind)
+
+
 def make_inputs(util: float, seed: int = 11):
     from paper_1710_11246_amd import slabhash as S
     from paper_1710_11246_amd import workload as W
@@ -797,6 +826,16 @@ def measure_alloc(n: int = 1 << 20, reps: int = 5) -> dict:
             tf.append(e[1].elapsed_time(e[2]))
         got = S.to_host_u32(out)
         assert np.unique(got).size == n and (got < pool).all()
+        # one more run with the operation counters on: claims lost to other wavefronts and
+        # moves to another block
+        t.reset()
+        t.set_launch(0, 0, S.SH_LAUNCH_COUNTERS)
+        S.sh_alloc_slabs(t.handle, n, out)
+        c = t.stats()
+        t.set_launch()
+        res[name + "_lost_claims"] = c["alloc_lost"]
+        res[name + "_block_moves"] = c["block_moves"]
+        assert c["allocs"] == n
         ms = float(np.median(ts))
         res[name + "_ms"] = round(ms, 4)
         res[name + "_Mslabs_per_s"] = round(n / (ms * 1e-3) / 1e6, 1)
@@ -846,6 +885,18 @@ def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
     return res
 
 
+def run_only(sections) -> dict:
+    """The named sections alone (no timed step), each as the full run reports it."""
+    runners = {"alloc": measure_alloc, "duplicates": measure_duplicates,
+               "keys_only": measure_keys_only, "batched": run_batched,
+               "concurrent": run_concurrent, "served": run_served}
+    out = {}
+    for name in sections:
+        log("section %s" % name)
+        out[name] = runners[name]()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -866,6 +917,10 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served-form section")
     ap.add_argument("--no-concurrent", action="store_true",
                     help="skip the incremental-growth and concurrent-batch section")
+    ap.add_argument("--only", default="",
+                    help="comma-separated sections to run alone, without the timed step (for "
+                         "profiling runs): alloc, flush, duplicates, keys_only, hbm, batched, "
+                         "concurrent, served")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device once (a reference "
                          "for scaling hardware traffic counters)")
@@ -881,6 +936,9 @@ def main():
     from paper_1710_11246_amd import workload as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     S.lib()
+    if args.only:
+        print(json.dumps(run_only(args.only.split(","))), flush=True)
+        return
 
     B = B_FOR_UTIL[args.util]
     log("generating inputs (n=2^22, B=%d)" % B)
@@ -976,18 +1034,14 @@ def main():
     S.sh_set_launch(h, args.waves_per_cu, 0, 0)
     util = 8.0 * stats_built["live"] / (256.0 * stats_built["slabs_total"])
 
-    # Algorithmic bytes per launch: every op reads its inputs and writes its outputs once and
-    # reads the 256-byte slabs its walk visits (v_hit / v_miss per op, from the table's bucket
-    # loads); an insert adds its 8-byte swap and each new slab a 4-byte link and a 4-byte
-    # bitmap word; a mixed batch's updates add one 8-byte swap each; a reset writes the table's
-    # header and base slabs and the pool slabs in use, and reads then zeroes the allocator
-    # bitmaps (a free pool slab is always empty already).
+    # Algorithmic bytes per launch (op_bytes): inputs and outputs once, the 256-byte slabs the
+    # walks read, 64 bytes per swap and 8 per new slab; a reset writes the table's header and
+    # base slabs and the pool slabs in use, and reads then zeroes the allocator bitmaps.
     bytes_l = {
-        "build": N_KEYS * (8 + 1 + 8) + 256.0 * v_hit * N_KEYS + new_slabs * (4 + 4),
-        "search_hit": N_KEYS * (4 + 4 + 1) + 256.0 * v_hit * N_KEYS,
-        "search_miss": N_KEYS * (4 + 4 + 1) + 256.0 * v_miss * N_KEYS,
-        "mixed": MIX_BATCH * (1 + 4 + 4 + 4 + 1) + 256.0 * (
-            (n_ins + n_miss) * v_miss + (n_del + n_hit) * v_hit) + 8.0 * (n_ins + n_del),
+        "build": op_bytes("insert", N_KEYS, v_hit, v_miss, new_slabs=new_slabs),
+        "search_hit": op_bytes("search_hit", N_KEYS, v_hit, v_miss),
+        "search_miss": op_bytes("search_miss", N_KEYS, v_hit, v_miss),
+        "mixed": op_bytes("mixed", MIX_BATCH, v_hit, v_miss, mix=(n_ins, n_del, n_hit, n_miss)),
         "reset": float(4096 + 256 * B + 256 * stats_end["pool_allocated"] +
                        2 * 256 * (table.params.pool_slabs // 2048)),
     }

@@ -39,3 +39,20 @@ def test_chain_visits_closed_form():
     for c in range(0, 101):
         want = sum(p // 31 + 1 for p in range(c))
         assert bench.chain_visits(np.array([c])) == want
+
+
+def test_op_bytes_model():
+    """Bytes per op of the roofline model: an insert reads its whole list (v_miss slabs) and
+    writes the 64-byte sector of its swapped slot; a delete reads to its key (v_hit) and writes
+    a sector; searches read their v slabs; a mixed batch adds its per-op inputs and outputs."""
+    vh, vm = 1.25, 2.5
+    assert bench.op_bytes("search_hit", 1, vh, vm) == 9 + 256 * vh
+    assert bench.op_bytes("search_miss", 1, vh, vm) == 9 + 256 * vm
+    assert bench.op_bytes("insert", 1, vh, vm) == 8 + 64 + 1 + 256 * vm
+    assert bench.op_bytes("insert", 10, vh, vm, new_slabs=3) == 10 * (73 + 256 * vm) + 24
+    assert bench.op_bytes("delete", 1, vh, vm) == 4 + 64 + 1 + 256 * vh
+    mix = bench.op_bytes("mixed", 10, vh, vm, mix=(2, 3, 4, 1))
+    assert mix == 10 * 14 + 256 * (3 * vm + 7 * vh) + 64 * 5 + 16 / 31
+    # the benchmark's build at 60% utilisation: 2^22 inserts
+    b = bench.op_bytes("insert", 1 << 22, 1.0006, 1.0052, new_slabs=20000)
+    assert abs(b / (1 << 22) - (73 + 256 * 1.0052)) < 0.05
