@@ -138,7 +138,7 @@ def test_duplicates_insert_only_build(M):
         assert len(WM.live_multiset(mem)) == n
 
 
-def unique_mixed_case(M, sd, plant=None):
+def unique_mixed_case(M, sd, plant=None, traces=None):
     B = 2
     base = [(k, 1000 + k) for k in range(4 * M)]
     fresh = [100, 102, 104, 101, 100]                      # key 100 twice
@@ -156,7 +156,9 @@ def unique_mixed_case(M, sd, plant=None):
               [WM.Op("insert", k, v) for k, v in reps] + [WM.Op("delete", k) for k in dels] + \
               [WM.Op("search", k) for k in srch]
         rng_order.shuffle(ops)
-        WM.run_schedule(mem, chunks_of(ops, [4, 3, 3, len(ops) - 10]), False, sd, plant)
+        tr = WM.run_schedule(mem, chunks_of(ops, [4, 3, 3, len(ops) - 10]), False, sd, plant)
+        if traces is not None:
+            traces.extend(tr)
         st100 = sorted(op.status for op in ops if op.key == 100)
         assert st100 == [1, 2]
         for op in ops:
@@ -206,3 +208,13 @@ def test_planted_mistakes_are_caught(plant, case):
         except AssertionError:
             return
     pytest.fail("planted mistake %s not caught" % plant)
+
+
+def test_schedules_reach_the_rare_paths():
+    """The schedules do reach the interleavings that matter: links lost to another wavefront,
+    and a new slab's slot 0 filled by another insert before the linking op's pair lands."""
+    tr = []
+    for sd in range(3000):
+        unique_mixed_case(4, sd, traces=tr)
+    kinds = {t[0] for t in tr}
+    assert "link" in kinds and "slot 0 taken before the pair" in kinds

@@ -11,10 +11,10 @@ Each wavefront takes a chunk of ops and works on it in rounds, as the HIP kernel
           A unique-key insert that loses its empty slot walks on with the occupants its swaps
           return; a duplicates-mode insert tries the other empty slots its snapshot showed;
           any other lost swap re-reads the slab next round;
-  grow    ops that found a full tail are served one at a time: take a free pool slab (a step),
-          with unique keys write the pair into its slot 0 first, link it with a swap on the
-          tail's next index (a step); a lost link takes the pair back out, frees the slab and
-          follows the winner's slab.
+  grow    ops that found a full tail each take a free pool slab (a step) and link it with a
+          swap on the tail's next index; with unique keys a swap of the pair into slot 0 of
+          the new slab is issued together with the link, the two landing in either order; a
+          lost link takes the pair back out, frees the slab and follows the winner's slab.
 A scheduler interleaves the steps of all wavefronts at random. The model shares nothing with
 the HIP code; it restates the protocol the kernel implements.
 
@@ -181,7 +181,44 @@ def wavefront(mem, ops, dup, rng, trace, plant=None):
                 gens.remove(g)
         done_ids = {id(op) for op in finished}
         todo = [op for op in todo if id(op) not in done_ids]
-        # ---- grow: one op at a time ----
+        # ---- grow: every op at a full tail takes a free pool slab (claimed together with the
+        # swaps above: a step of its own), then links it with a swap on its tail's next index.
+        # With unique keys the pair goes into slot 0 of the new slab with a swap issued
+        # together with the link, so the two land in either order: a link that lands first
+        # makes the slab public, and another insert may fill slot 0 before the pair does (this
+        # op then takes the next round on the new slab). A lost link leaves the slab private:
+        # its pair is taken out and the slab freed, and the op follows the winner's slab. ----
+        def link(op, u, idx):
+            fresh = mem.B + idx
+            put = None
+            order = ["prefill", "link"] if not dup else ["link"]
+            rng.shuffle(order)
+            lold = "pending"
+            for step in order:
+                yield
+                if step == "prefill":
+                    put = mem.cas_slot(fresh, 0, None, (op.key, op.val))
+                else:
+                    lold = mem.cas_next(u, None, idx)
+            if lold is None:
+                trace.append(("link", u, idx))
+                if not dup and put is None:
+                    op.status = 1
+                    finished.append(op)
+                else:
+                    if not dup:
+                        trace.append(("slot 0 taken before the pair", u, idx))
+                    op.cursor = idx
+            else:
+                if not dup and put is None and plant != "no_takeback":
+                    yield
+                    assert mem.cas_slot(fresh, 0, (op.key, op.val), None) == (op.key, op.val)
+                yield
+                mem.allocated[idx] = False
+                op.cursor = lold
+
+        finished = []
+        gens = []
         for op, u in grow:
             yield
             free = [i for i in range(mem.P) if not mem.allocated[i]]
@@ -191,30 +228,19 @@ def wavefront(mem, ops, dup, rng, trace, plant=None):
                 trace.append(("pool exhausted", op.key))
                 continue
             idx = rng.choice(free)
+            assert mem.slots[mem.B + idx] == [None] * M and mem.next[mem.B + idx] is None, \
+                "an allocated slab is not empty"
             mem.allocated[idx] = True
-            fresh = mem.B + idx
-            put = False
-            if not dup:
-                # the slab is private until linked: the pair goes into its slot 0 first
-                assert mem.slots[fresh] == [None] * M and mem.next[fresh] is None, \
-                    "an allocated slab is not empty"
-                mem.slots[fresh][0] = (op.key, op.val)
-                put = True
-            yield
-            old = mem.cas_next(u, None, idx)
-            if old is None:
-                trace.append(("link", u, idx))
-                if put:
-                    op.status = 1
-                    todo.remove(op)
-                else:
-                    op.cursor = idx
-            else:
+            gens.append(link(op, u, idx))
+        while gens:
+            g = rng.choice(gens)
+            try:
+                next(g)
                 yield
-                if put and plant != "no_takeback":
-                    assert mem.cas_slot(fresh, 0, (op.key, op.val), None) == (op.key, op.val)
-                mem.allocated[idx] = False
-                op.cursor = old
+            except StopIteration:
+                gens.remove(g)
+        done_ids = {id(op) for op in finished}
+        todo = [op for op in todo if id(op) not in done_ids]
 
 
 def run_schedule(mem, chunks, dup, seed, plant=None):
