@@ -47,6 +47,8 @@ TRAFFIC_SRC_SHA = "02295a463c8ca04f"
 # reached memory).
 L2_STATS = {"build": (0.3643, 4796460, 4796460), "search_hit": (0.0943, 0, 0), "search_miss": (0.0943, 0, 0),
             "mixed": (0.2812, 26740, 26740), "reset": (0.5032, 0, 0)}
+# The same for the 2^26-key table of measure_hbm_resident (bytes per launch).
+HBM_TRAFFIC_BYTES = {}
 TRAFFIC_BYTES = {"build": 1355416374, "search_hit": 1039118007, "search_miss": 1039118007,
                  "mixed": 19357748, "reset": 55896689}
 
@@ -248,8 +250,8 @@ def run_batched(seed: int = 31, T: int = 256, rounds: int = 20, wpc_override: in
     Buckets and pools come from the autotuner's Binomial model for utilisation 0.6 at each
     table's final occupancy; the batched launch shape is picked by timing candidates on round 0.
     Three forms run the same rounds on identically built tables: one sh_mixed launch per table,
-    one batched launch per round, and one graph replay per round (after copying the round's
-    descriptors into the graph's buffer). Returns a dict of results."""
+    one batched launch per round, and all rounds' batched launches captured into one graph and
+    replayed once. Returns a dict of results."""
     import torch
     from paper_1710_11246_amd import autotune as A
     from paper_1710_11246_amd import slabhash as S
@@ -320,16 +322,18 @@ def run_batched(seed: int = 31, T: int = 256, rounds: int = 20, wpc_override: in
                                                 all_vals, vout, sout) for r in range(rounds)])
     mut = torch.from_numpy(np.concatenate(mr.ops) != 0).to("cuda")
     same_plain = bool(((sout == st_plain) | ~mut).all())
-    # (iii) graph replay per round
+    # (iii) every round's batched launch captured once into one graph (sh_capture_begin/end
+    # on a side stream), replayed as a single submission
     rebuild()
-    desc_buf = torch.empty_like(descs[0])
-    g = S.sh_multi_graph(m.handle, desc_buf, T, all_ops, all_keys, all_vals, vout, sout)
+    cs = torch.cuda.Stream()
+    S.sh_capture_begin(cs)
     try:
-        def graphed():
-            for r in range(rounds):
-                desc_buf.copy_(descs[r])
-                S.sh_graph_launch(g)
-        t_graph = timed(graphed)
+        for r in range(rounds):
+            S.sh_multi_mixed(m.handle, descs[r], T, all_ops, all_keys, all_vals, vout, sout, cs)
+    finally:
+        g = S.sh_capture_end(cs)
+    try:
+        t_graph = timed(lambda: S.sh_graph_launch(g))
     finally:
         S.sh_graph_destroy(g)
     same_graph = bool(((sout == st_plain) | ~mut).all())
@@ -622,6 +626,82 @@ def sweep_sizes(log2_sizes=(16, 18, 20, 22, 24, 26), util: float = 0.6, reps: in
     return out
 
 
+def measure_hbm_resident(log2n: int = 26, util: float = 0.6, reps: int = 3,
+                         seed: int = 61) -> dict:
+    """A table far larger than the 256 MB Infinity Cache: bulk build of 2^26 distinct uniform
+    keys into the bucket count whose Binomial-model utilisation is 0.6 (about 0.9 GB of base
+    slabs), then 2^26 all-hit searches (a permutation of the keys) and 2^26 all-miss searches.
+    Median of `reps` runs after one untimed run, each build on a reset table, HIP events around
+    each call. Every status, found flag and hit value is checked on the device. Algorithmic
+    bytes follow op_bytes with the built table's own slabs per hit and per miss."""
+    import torch
+    from paper_1710_11246_amd import autotune as A
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    n = 1 << log2n
+    keys = W.distinct_keys(seed, 0, n)
+    miss = W.distinct_keys(seed, n, n)
+    perm = W.SplitMix64(seed + 1).permutation(n)
+    rng = W.SplitMix64(seed + 2)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    B = A.buckets_for_utilisation(n, util)
+    t = S.SlabHash(B, A.pool_slabs_for(n, B), a, b)
+    vals = W.value_of(keys)
+    kd, vd = S.to_dev(keys), S.to_dev(vals)
+    qh, qm = S.to_dev(keys[perm]), S.to_dev(miss)
+    want = S.to_dev(vals[perm])
+    del keys, miss, perm, vals
+    st = torch.empty(n, dtype=torch.uint8, device="cuda")
+    vo = torch.empty(n, dtype=torch.int32, device="cuda")
+    fo = torch.empty(n, dtype=torch.uint8, device="cuda")
+    names = ("build", "search_hit", "search_miss")
+    res = {k: [] for k in names}
+    for rep in range(reps + 1):
+        t.reset()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        S.sh_build(t.handle, kd, vd, st)
+        e[1].record()
+        S.sh_search(t.handle, qh, vo, fo)
+        e[2].record()
+        ok_hit = bool((fo == 1).all()) and bool((vo == want).all())
+        S.sh_search(t.handle, qm, vo, fo)
+        e[3].record()
+        torch.cuda.synchronize()
+        assert bool((st == 1).all()) and ok_hit and not bool(fo.any())
+        if rep:
+            for i, k in enumerate(names):
+                res[k].append(e[i].elapsed_time(e[i + 1]))
+    su = t.stats()
+    counts = torch.empty(3 * B, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    viol = torch.zeros(1, dtype=torch.int32, device="cuda")
+    S.sh_dump(t.handle, None, None, None, counts, cnt, viol)
+    c = S.to_host_u32(counts).reshape(-1, 3)
+    assert int(viol.item()) == 0 and int(cnt.item()) == n
+    v_hit = chain_visits(c[:, 0].astype(np.int64) + c[:, 1]) / n
+    v_miss = float(c[:, 2].mean())
+    bytes_l = {"build": op_bytes("insert", n, v_hit, v_miss, new_slabs=su["pool_allocated"]),
+               "search_hit": op_bytes("search_hit", n, v_hit, v_miss),
+               "search_miss": op_bytes("search_miss", n, v_hit, v_miss)}
+    traffic_ok = source_sha() == TRAFFIC_SRC_SHA
+    out = {"workload": "bulk build of 2^%d uniform uint32 keys, then 2^%d all-hit and 2^%d "
+                       "all-miss searches" % (log2n, log2n, log2n),
+           "keys": n, "num_buckets": B, "table_bytes": int(t.storage.numel()),
+           "utilisation": round(8.0 * su["live"] / (256.0 * su["slabs_total"]), 4),
+           "slabs_per_hit": round(v_hit, 4), "slabs_per_miss": round(v_miss, 4)}
+    for k in names:
+        ms = float(np.median(res[k]))
+        gbs = bytes_l[k] / (ms * 1e-3) / 1e9
+        out[k] = {"avg_ms": round(ms, 4), "Mops": round(n / (ms * 1e-3) / 1e6, 1),
+                  "bytes_per_launch": int(bytes_l[k]), "algorithmic_GBps": round(gbs, 1),
+                  "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                  "traffic_bytes": HBM_TRAFFIC_BYTES.get(k) if traffic_ok else None}
+    del t, kd, vd, qh, qm, want, st, vo, fo
+    torch.cuda.empty_cache()
+    return out
+
+
 def sweep_batches(log2_batches=(15, 16, 17), total: int = 1 << 24, B: int = 793240) -> dict:
     """Incremental insertion ("Incremental insertion"): 2^24 distinct keys inserted in batches of
     each size into a table whose final utilisation is about 0.65; the rate over all batches and
@@ -887,7 +967,8 @@ def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
 
 def run_only(sections) -> dict:
     """The named sections alone (no timed step), each as the full run reports it."""
-    runners = {"alloc": measure_alloc, "duplicates": measure_duplicates,
+    runners = {"alloc": measure_alloc, "hbm": measure_hbm_resident,
+               "duplicates": measure_duplicates,
                "keys_only": measure_keys_only, "batched": run_batched,
                "concurrent": run_concurrent, "served": run_served}
     out = {}
@@ -913,6 +994,8 @@ def main():
                     help="also time build/search for table sizes 2^16 .. 2^26 at utilisation 0.6")
     ap.add_argument("--sweep-batches", action="store_true",
                     help="also time incremental insertion to 2^24 keys in batches of 2^15..2^17")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only the timed step and its per-kernel figures (no other section)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form section")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form section")
     ap.add_argument("--no-concurrent", action="store_true",
@@ -1072,31 +1155,35 @@ def main():
             "traffic": TRAFFIC_BYTES[dom] if traffic_ok else None, "kernel": dom,
             "bytes_per_launch": int(bytes_l[dom])}
 
-    log("flush")
-    flush = measure_flush(table, keys, vals, st_build, stream)
+    if args.step_only:
+        args.no_batched = args.no_served = args.no_concurrent = args.no_cpu_baseline = True
+    flush = allocator = duplicates = keys_only = hbm = patterns = None
+    if not args.step_only:
+        log("flush")
+        flush = measure_flush(table, keys, vals, st_build, stream)
+        log("allocator")
+        allocator = measure_alloc()
+        log("duplicates")
+        duplicates = measure_duplicates()
+        log("keys only")
+        keys_only = measure_keys_only()
+        log("HBM-resident table (2^26 keys)")
+        hbm = measure_hbm_resident()
+        log("access-pattern ceilings")
+        patterns = measure_patterns(int(table.storage.numel()), N_KEYS)
+        # each kernel against the ceiling of its own access pattern, measured above
+        pattern_of = {"build": "load_cas", "search_hit": "slab_load", "search_miss": "slab_load"}
+        for k, pat in pattern_of.items():
+            kernels[k]["pattern_ceiling_us"] = patterns[pat + "_us"]
+            kernels[k]["frac_of_pattern_ceiling"] = round(patterns[pat + "_us"] /
+                                                          (avg_ms[k] * 1e3), 4)
+        if dom in pattern_of:
+            roof["secondary"] = {
+                "bound": "atomic" if dom == "build" else "hbm",
+                "pattern": pattern_of[dom], "ceiling_us": patterns[pattern_of[dom] + "_us"],
+                "kernel_us": round(avg_ms[dom] * 1e3, 1),
+                "frac": kernels[dom]["frac_of_pattern_ceiling"]}
 
-    log("allocator")
-    allocator = measure_alloc()
-
-    log("duplicates")
-    duplicates = measure_duplicates()
-    log("keys only")
-    keys_only = measure_keys_only()
-
-    log("access-pattern ceilings")
-    patterns = measure_patterns(int(table.storage.numel()), N_KEYS)
-    # each kernel against the ceiling of its own access pattern, measured above
-    pattern_of = {"build": "load_cas", "search_hit": "slab_load", "search_miss": "slab_load"}
-    for k, pat in pattern_of.items():
-        kernels[k]["pattern_ceiling_us"] = patterns[pat + "_us"]
-        kernels[k]["frac_of_pattern_ceiling"] = round(patterns[pat + "_us"] /
-                                                      (avg_ms[k] * 1e3), 4)
-    if dom in pattern_of:
-        roof["secondary"] = {
-            "bound": "atomic" if dom == "build" else "hbm",
-            "pattern": pattern_of[dom], "ceiling_us": patterns[pattern_of[dom] + "_us"],
-            "kernel_us": round(avg_ms[dom] * 1e3, 1),
-            "frac": kernels[dom]["frac_of_pattern_ceiling"]}
 
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
@@ -1177,6 +1264,7 @@ def main():
         "allocator": allocator,
         "duplicates": duplicates,
         "keys_only": keys_only,
+        "hbm_resident": hbm,
         "cpu_baseline": cpu,
         "cpu_partitioned": cpu_part,
     }

@@ -6,8 +6,9 @@
  * of a slab list ("Slab list" subsection). Slabs are 256 bytes: 31 key/value slots of 8 bytes
  * (key in the low 32 bits, value in the high 32 bits), then one 8-byte word holding an auxiliary
  * 32-bit field and the 32-bit index of the next slab. Extra slabs come from a pool managed by a
- * wavefront-synchronous bitmap allocator in blocks of 2048 slabs ("Dynamic memory allocation",
- * SlabAlloc with all blocks in one contiguous array). A wavefront of 64 lanes processes the
+ * wavefront-synchronous bitmap allocator in blocks of 2048 slabs ("Dynamic memory allocation":
+ * SlabAlloc; the table's own pool is one contiguous array, and further super blocks can be
+ * registered, see sh_add_super_block). A wavefront of 64 lanes processes the
  * operations its lanes hold one at a time ("warp-cooperative work sharing").
  *
  * Conventions for every call:
@@ -75,7 +76,8 @@ enum { SH_TABLE_DUPLICATES = 1u, SH_TABLE_KEYS_ONLY = 2u };
 
 typedef struct {
     uint32_t num_buckets; /* B >= 1 */
-    uint32_t pool_slabs;  /* slabs beyond the base slabs; a multiple of SH_BLOCK_SLABS, may be 0 */
+    uint32_t pool_slabs;  /* slabs beyond the base slabs (super block 0): a multiple of
+                             SH_BLOCK_SLABS, at most 2^27 - 2048, may be 0 */
     uint32_t hash_a;      /* 1 <= a < p */
     uint32_t hash_b;      /* 0 <= b < p */
     uint32_t flags;       /* SH_TABLE_DUPLICATES and/or SH_TABLE_KEYS_ONLY; other bits invalid */
@@ -115,8 +117,10 @@ typedef struct {
     /* Operation counters since create/reset, summed over wavefronts, accumulated only while
        SH_LAUNCH_COUNTERS is set: decision rounds (one per chunk of ops and pass over it), swaps
        lost to another wavefront, slabs allocated, links lost (slab freed again), allocator
-       moves to another block. */
-    uint64_t rounds, cas_lost, allocs, link_lost, block_moves;
+       moves to another block, allocator claims that found their bitmap bit already taken by
+       another wavefront (sh_alloc_slabs counts its allocations, block moves and lost claims
+       here too). */
+    uint64_t rounds, cas_lost, allocs, link_lost, block_moves, alloc_lost;
 } sh_stats_t;
 
 /* Device bytes a table with these parameters needs (header + base slabs + pool + bitmaps).
@@ -164,6 +168,31 @@ sh_status_t sh_alloc_slabs(sh_table_t *t, uint64_t n, uint32_t *d_out, void *str
    list and still be empty (all ones), as allocation hands them out: allocations do not clear
    slabs. n < 2^32, else SH_EINVAL. Asynchronous; must not overlap other calls on the table. */
 sh_status_t sh_free_slabs(sh_table_t *t, const uint32_t *d_idx, uint64_t n, void *stream);
+
+/* Super blocks ("Dynamic memory allocation": SlabAlloc's pool is a set of super blocks, each
+   of memory blocks of memory units, addressed by one 32-bit word). A table's own pool is its
+   super block 0. sh_add_super_block registers caller-owned device memory d_mem (256-byte
+   aligned) as the table's next super block: the most slabs S (a multiple of SH_BLOCK_SLABS,
+   at most 2^27 - 2048) whose S * 256 bytes of slabs plus S / 2048 bitmap rows of 256 bytes fit
+   in `bytes` (sh_super_block_bytes(S) gives the bytes for S slabs), laid out as those slabs
+   followed by their bitmap rows. It enqueues the memory's initialisation (every slab empty,
+   every bitmap bit free) and the super block's entry in the table's directory on `stream`.
+   A pool slab's address, the next index stored in a slab, is then its super block in the top
+   5 bits and its slab within the super block in the low 27 (allocator block in bits 26..11,
+   slab within the block in bits 10..0); super block 0's addresses are its plain slab indices.
+   The allocator hands out slabs of the super blocks it is using and moves on to the next
+   registered super block only once a full cycle of those finds no free slab, so memory
+   registered ahead of need is used when the pool would otherwise run out (an insert fails
+   with the pool-exhausted error only when every registered super block is full). At most
+   SH_MAX_SUPER_BLOCKS super blocks per table, super block 0 included; sh_reset keeps them
+   registered and empties them; sh_stats counts them in pool_capacity and pool_allocated.
+   Must not overlap other calls on the table (a server started earlier does not see later
+   super blocks). SH_EINVAL for a NULL or misaligned d_mem, fewer bytes than one block, or a
+   table that already has SH_MAX_SUPER_BLOCKS. The memory stays the caller's and must outlive
+   the table's use. */
+#define SH_MAX_SUPER_BLOCKS 32u
+size_t sh_super_block_bytes(uint32_t slabs); /* 0 unless a positive multiple of 2048, <= 2^27 - 2048 */
+sh_status_t sh_add_super_block(sh_table_t *t, void *d_mem, size_t bytes, void *stream);
 
 /* Free the host handle only; the device storage stays the caller's. Handles that belong to a
    multi-table object (sh_multi_table) give SH_EINVAL. */
@@ -311,6 +340,22 @@ sh_status_t sh_multi_graph(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_
                            const uint8_t *d_ops, const uint32_t *d_keys,
                            const uint32_t *d_vals_in, uint32_t *d_vals_out, uint8_t *d_status,
                            uint64_t n_ops, sh_graph_t **out);
+
+/* Capture instead of run: the work that the calls made from this host thread enqueue on
+   `stream` between sh_capture_begin and sh_capture_end is recorded into one HIP graph, which
+   sh_graph_launch replays as a single submission (a sequence of many short launches, such as a
+   round of batched launches or a whole build-search-mixed pass, then pays one launch cost).
+   Every call that only enqueues kernels may be captured: sh_reset, sh_build, sh_insert,
+   sh_delete, sh_search, sh_mixed, sh_flush, sh_search_all, sh_delete_all, sh_alloc_slabs,
+   sh_free_slabs, sh_multi_mixed and sh_multi_mixed_each. A replay runs them with the
+   arguments given at capture (the same pointers, sizes and launch shapes) on whatever the
+   buffers hold when it runs. Calls that synchronise or read results on the host (sh_stats,
+   sh_dump, the server) must not be made on a capturing stream. The NULL stream cannot be
+   captured (SH_EINVAL), nor one already capturing. sh_capture_end returns SH_EHIP if the
+   capture failed (a call above made an uncapturable request); the stream is then no longer
+   capturing either way. */
+sh_status_t sh_capture_begin(void *stream);
+sh_status_t sh_capture_end(void *stream, sh_graph_t **out);
 
 /* Replay a captured graph on `stream`. */
 sh_status_t sh_graph_launch(sh_graph_t *g, void *stream);

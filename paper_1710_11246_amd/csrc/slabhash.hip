@@ -44,7 +44,7 @@ constexpr uint64_t kSlotMask = 0x7FFFFFFFull;         // slots 0..30 of a half w
 constexpr uint32_t kPrime = SH_HASH_PRIME;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr size_t kHeaderBytes = 4096;   // Header, then the counter slots
+constexpr size_t kHeaderBytes = 4096;   // Header, counter slots, super-block directory
 constexpr uint32_t kCounterSlots = 32;   // 64-byte slots of 8 counters, one per wavefront % 32
 constexpr uint32_t kFlagCounters = SH_LAUNCH_COUNTERS;
 constexpr uint32_t kMaxBatches = SH_MAX_BATCHES;
@@ -61,13 +61,41 @@ struct Header {
     unsigned long long live, tomb, slabs, pool_alloc, dump_count;
 };
 
+// Super blocks ("Dynamic memory allocation"): super block 0 is the table's own pool, which
+// directly follows the base slabs; super blocks 1 .. nsuper-1 are further caller-owned regions
+// of slabs and bitmap rows, registered with sh_add_super_block. A pool slab's 32-bit address
+// (the next index of a slab, an op's cursor) is its super block in the top 5 bits and its slab
+// within the super block below (allocator block in bits 26..11, slab within the block in bits
+// 10..0), so super block 0's addresses are plain pool indices. The allocator numbers the blocks
+// of all super blocks in order of registration and moves on to the next super block only when
+// a full cycle over the ones in use found no free slab.
+constexpr uint32_t kSuperShift = 27;
+constexpr uint32_t kSlabInSuper = (1u << kSuperShift) - 1u;
+constexpr uint32_t kMaxSupers = SH_MAX_SUPER_BLOCKS;
+constexpr uint32_t kMaxSuperSlabs = (1u << kSuperShift) - SH_BLOCK_SLABS;
+
+struct SuperDesc {
+    uint64_t *pool;   // its slab 0
+    uint32_t *bitmap; // its bitmap rows
+    uint32_t slabs;   // a multiple of SH_BLOCK_SLABS
+    uint32_t first;   // allocator number of its first block
+};
+// Header bytes: [0, 256) Header, [256, 2304) counter slots, then the super-block directory, then
+// the number of super blocks beyond super block 0 the allocator has moved on to.
+constexpr size_t kDirOffset = 2304;
+constexpr size_t kGrownOffset = kDirOffset + kMaxSupers * sizeof(SuperDesc);
+static_assert(kGrownOffset + 16 <= 4096, "the directory fits in the header");
+
 struct View {
     uint64_t *base;   // B slabs of 32 words
-    uint64_t *pool;   // P slabs of 32 words
-    uint32_t *bitmap; // P/2048 rows of 64 words
+    uint64_t *pool;   // super block 0: P slabs of 32 words
+    uint32_t *bitmap; // super block 0: P/2048 rows of 64 words
     Header *hdr;
     unsigned long long *counters; // kCounterSlots x 8
+    const SuperDesc *dir;         // entries 1 .. nsuper-1 in use (entry 0 is pool/bitmap above)
+    uint32_t *grown;              // super blocks beyond 0 the allocator has moved on to
     uint32_t B, a, b, pool_slabs, nblk;
+    uint32_t nsuper, total_blocks; // super blocks registered, allocator blocks in all of them
     uint32_t mode; // SH_TABLE_DUPLICATES | SH_TABLE_KEYS_ONLY bits of the table's flags
 };
 
@@ -176,34 +204,145 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
 }
 
 // ---------------------------------------------------------------------------------------------
-// SlabAlloc for wave64 ("Dynamic memory allocation"). The pool is one contiguous array of
-// blocks of 2048 slabs; a block's occupancy is one 256-byte bitmap row, which a wavefront holds
-// in registers as one 32-bit word per lane (lane l covers slabs 32l .. 32l+31 of the block).
-// The wavefront's "resident" block serves its allocations: lanes with a free bit vote, the
-// first such lane in the wavefront's own priority order (lane order rotated by a per-wavefront
-// offset) claims its lowest free bit with an atomic OR on the row in memory and, if the bit was
-// still free, broadcasts the slab index. A lost race refreshes that lane's word. When
-// the resident block is full the wavefront moves to the next block, reading its row with one
-// coalesced load; after a full cycle of blocks without success the pool counts as exhausted.
+// SlabAlloc for wave64 ("Dynamic memory allocation"). The pool is made of super blocks, each a
+// contiguous array of blocks of 2048 slabs; a block's occupancy is one 256-byte bitmap row,
+// which a wavefront holds in registers as one 32-bit word per lane (lane l covers slabs
+// 32l .. 32l+31 of the block). The wavefront's "resident" block serves its allocations: lanes
+// with a free bit vote, the first such lane in the wavefront's own priority order (lane order
+// rotated by a per-wavefront offset) claims its lowest free bit with an atomic OR on the row in
+// memory and, if the bit was still free, broadcasts the slab address. A lost race refreshes
+// that lane's word. When the resident block is full the wavefront moves to the next block,
+// reading its row with one coalesced load; after a full cycle of the blocks in use without
+// success it moves on to the next registered super block, and with none left the pool counts
+// as exhausted.
+
+// Pool slab `idx` (a 32-bit pool address) and a cursor's slab (kEmpty = the bucket's base slab).
+__device__ __forceinline__ uint64_t *pool_slab(const View &T, uint32_t idx)
+{
+    const uint32_t sb = idx >> kSuperShift;
+    if (sb == 0)
+        return T.pool + (size_t)idx * 32;
+    return T.dir[sb].pool + (size_t)(idx & kSlabInSuper) * 32;
+}
+
+__device__ __forceinline__ uint64_t *cursor_slab(const View &T, uint32_t loc, uint32_t bkt)
+{
+    return loc == kEmpty ? T.base + (size_t)bkt * 32 : pool_slab(T, loc);
+}
+
+// Whether `idx` addresses a slab of a registered super block.
+__device__ __forceinline__ bool pool_in_range(const View &T, uint32_t idx)
+{
+    const uint32_t sb = idx >> kSuperShift;
+    if (sb == 0)
+        return idx < T.pool_slabs;
+    return sb < T.nsuper && (idx & kSlabInSuper) < T.dir[sb].slabs;
+}
+
+// The bitmap word holding pool slab idx's bit (bit idx mod 32).
+__device__ __forceinline__ uint32_t *bitmap_word(const View &T, uint32_t idx)
+{
+    const uint32_t sb = idx >> kSuperShift, i = idx & kSlabInSuper;
+    uint32_t *bm = sb ? T.dir[sb].bitmap : T.bitmap;
+    return bm + (size_t)(i >> 11) * 64 + ((i >> 5) & 63);
+}
+
+// Allocator block g (numbered over all registered super blocks): its bitmap row and the
+// address of its first slab.
+__device__ __forceinline__ void block_ref(const View &T, uint32_t g, uint32_t *&row,
+                                          uint32_t &code)
+{
+    if (g < T.nblk) {
+        row = T.bitmap + (size_t)g * 64;
+        code = g * SH_BLOCK_SLABS;
+        return;
+    }
+    uint32_t sb = 1;
+    while (sb + 1 < T.nsuper && T.dir[sb + 1].first <= g)
+        ++sb;
+    const uint32_t lb = g - T.dir[sb].first;
+    row = T.dir[sb].bitmap + (size_t)lb * 64;
+    code = (sb << kSuperShift) | (lb * SH_BLOCK_SLABS);
+}
+
+// Blocks of super block 0 and of the `grown` super blocks after it.
+__device__ __forceinline__ uint32_t blocks_in_use(const View &T, uint32_t grown)
+{
+    return 1 + grown >= T.nsuper ? T.total_blocks : T.dir[1 + grown].first;
+}
 
 struct Alloc {
     uint32_t blk;   // resident block (wave-uniform), kEmpty = none yet
     uint32_t word;  // this lane's bitmap word of the resident block
+    uint32_t *row;  // the resident block's bitmap row
+    uint32_t code;  // address of the resident block's first slab
+    uint32_t nact;  // blocks in use (super blocks the allocator has reached)
     uint32_t moves; // block moves since the last successful allocation
     uint32_t total_moves;
-    uint32_t start; // first block tried
+    uint32_t start; // first block tried (taken modulo the blocks in use)
     uint32_t rot;   // this wavefront's rotation of the lane priority order
+    uint32_t lost;  // claims that found their bit already taken by another wavefront
     bool full;      // this wavefront found the pool exhausted
 };
 
+__device__ __forceinline__ void alloc_goto(const View &T, Alloc &s, uint32_t g, uint32_t lane)
+{
+    s.blk = g;
+    block_ref(T, g, s.row, s.code);
+    s.word = load_word_coherent(&s.row[lane]);
+}
+
+// A full cycle over the blocks in use found no free slab: move on to the first block of the
+// next registered super block (the first wavefront to get here records the move for all), or
+// report that there is none.
+__device__ bool alloc_grow(const View &T, Alloc &s, uint32_t lane)
+{
+    if (T.nsuper == 1)
+        return false;
+    uint32_t g = load_word_coherent(T.grown);
+    if (blocks_in_use(T, g) <= s.nact && 1 + g < T.nsuper) {
+        uint32_t old = 0;
+        if (lane == 0)
+            old = cas32(T.grown, g, g + 1);
+        old = rl(old, 0);
+        g = (old == g) ? g + 1 : old; // another wavefront may have moved on already
+    }
+    const uint32_t n = blocks_in_use(T, g);
+    if (n <= s.nact)
+        return false;
+    const uint32_t first = s.nact;
+    s.nact = n;
+    s.moves = 0;
+    alloc_goto(T, s, first, lane);
+    return true;
+}
+
+// The wavefront's first block, its bitmap row read ahead of any need (kernels that may grow
+// lists call this at their start, so the first allocation costs one atomic, not a row read and
+// an atomic).
+__device__ __forceinline__ void alloc_preload(const View &T, Alloc &s, uint32_t lane)
+{
+    if (T.total_blocks == 0 || s.blk != kEmpty)
+        return;
+    s.nact = T.nsuper == 1 ? T.nblk : blocks_in_use(T, load_word_coherent(T.grown));
+    s.moves = 0;
+    if (s.nact == 0) {
+        // the table's own pool is empty: start in the first registered super block
+        if (!alloc_grow(T, s, lane))
+            s.full = true;
+        return;
+    }
+    alloc_goto(T, s, s.start % s.nact, lane);
+}
+
 __device__ uint32_t wave_alloc(const View &T, Alloc &s, uint32_t lane)
 {
-    if (T.nblk == 0 || s.full)
+    if (T.total_blocks == 0 || s.full)
         return kEmpty;
     if (s.blk == kEmpty) {
-        s.blk = s.start % T.nblk;
-        s.moves = 0;
-        s.word = load_word_coherent(&T.bitmap[(size_t)s.blk * 64 + lane]);
+        alloc_preload(T, s, lane);
+        if (s.full)
+            return kEmpty;
     }
     for (;;) {
         const uint64_t free_lanes = ballot(s.word != kEmpty);
@@ -217,34 +356,131 @@ __device__ uint32_t wave_alloc(const View &T, Alloc &s, uint32_t lane)
             if (lane == l) {
                 const uint32_t bit = (uint32_t)__builtin_ctz(~s.word);
                 const uint32_t m = 1u << bit;
-                const uint32_t old =
-                    __hip_atomic_fetch_or(&T.bitmap[(size_t)s.blk * 64 + l], m,
-                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t old = __hip_atomic_fetch_or(&s.row[l], m, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
                 s.word = old | m;
                 if (!(old & m))
-                    got = s.blk * SH_BLOCK_SLABS + l * 32 + bit;
+                    got = s.code + l * 32 + bit;
             }
             const uint32_t idx = rl(got, l);
             if (idx != kEmpty) {
                 s.moves = 0;
                 return idx;
             }
+            ++s.lost;
             continue;
         }
-        if (++s.moves > T.nblk) {
+        if (++s.moves > s.nact) {
+            if (alloc_grow(T, s, lane))
+                continue;
             s.full = true;
             return kEmpty;
         }
         ++s.total_moves;
-        s.blk = (s.blk + 1 == T.nblk) ? 0 : s.blk + 1;
-        s.word = load_word_coherent(&T.bitmap[(size_t)s.blk * 64 + lane]);
+        alloc_goto(T, s, (s.blk + 1 >= s.nact) ? 0 : s.blk + 1, lane);
     }
+}
+
+// Exclusive prefix sum of x over the lanes in this wavefront's rotated order (lane rot first),
+// and the total over all lanes.
+__device__ __forceinline__ uint32_t rotated_scan(uint32_t x, uint32_t lane, uint32_t rot,
+                                                 uint32_t *total)
+{
+    const uint32_t pos = (lane - rot) & 63u;
+    uint32_t incl = x;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t t = (uint32_t)__shfl((int)incl, (int)((lane - d) & 63u), 64);
+        if (pos >= d)
+            incl += t;
+    }
+    *total = (uint32_t)__shfl((int)incl, (int)((rot + 63u) & 63u), 64);
+    return incl - x;
+}
+
+// Serve `need` (<= 64) allocations of this wavefront together from its resident block: the
+// lanes whose bitmap words hold free bits claim, in the wavefront's rotated lane order, as many
+// as are still needed, each with one atomic OR of several bits; bits another wavefront took in
+// the meantime are left to the next pass. The j-th slab claimed (rotated lane order, then bit
+// order) is written by its lane to out[j]. Moves on to the next block as wave_alloc does.
+// Returns how many were served: `need`, unless the pool is exhausted.
+__device__ uint32_t wave_alloc_many(const View &T, Alloc &s, uint32_t lane, uint32_t need,
+                                    uint32_t *__restrict__ out)
+{
+    if (T.total_blocks == 0 || s.full)
+        return 0;
+    if (s.blk == kEmpty) {
+        alloc_preload(T, s, lane);
+        if (s.full)
+            return 0;
+    }
+    uint32_t got = 0;
+    while (got < need) {
+        const uint32_t fw = ~s.word;
+        uint32_t total;
+        const uint32_t before = rotated_scan((uint32_t)__popc(fw), lane, s.rot, &total);
+        if (total == 0) {
+            if (++s.moves > s.nact) {
+                if (alloc_grow(T, s, lane))
+                    continue;
+                s.full = true;
+                break;
+            }
+            ++s.total_moves;
+            alloc_goto(T, s, (s.blk + 1 >= s.nact) ? 0 : s.blk + 1, lane);
+            continue;
+        }
+        // this lane's share: its lowest free bits, up to what the lanes before it leave over
+        const uint32_t left = need - got;
+        uint32_t take = before >= left ? 0u : left - before;
+        uint32_t m = 0, f = fw;
+        for (; take && f; --take) {
+            m |= f & (0u - f);
+            f &= f - 1u;
+        }
+        uint32_t mine = 0;
+        if (m) {
+            const uint32_t old =
+                __hip_atomic_fetch_or(&s.row[lane], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            mine = m & ~old;
+            s.word = old | m;
+        }
+        s.lost += (uint32_t)__popcll(ballot((m & ~mine) != 0u));
+        uint32_t served;
+        uint32_t at = got + rotated_scan((uint32_t)__popc(mine), lane, s.rot, &served);
+        for (uint32_t w = mine; w; w &= w - 1u)
+            out[at++] = s.code + lane * 32 + (uint32_t)__builtin_ctz(w);
+        got += served;
+        if (served)
+            s.moves = 0;
+    }
+    return got;
+}
+
+// The bits this lane claims so that the wavefront's lanes together claim `need` free slabs of
+// the resident block (in the rotated lane order of wave_alloc_many, lowest free bits first); 0
+// for every lane when there is no resident block yet. Fewer than `need` when the block holds
+// fewer free slabs.
+__device__ __forceinline__ uint32_t claim_plan(const Alloc &s, uint32_t lane, uint32_t need)
+{
+    if (s.blk == kEmpty || s.full)
+        return 0u;
+    const uint32_t fw = ~s.word;
+    uint32_t total;
+    const uint32_t before = rotated_scan((uint32_t)__popc(fw), lane, s.rot, &total);
+    uint32_t take = before >= need ? 0u : need - before;
+    uint32_t m = 0, f = fw;
+    for (; take && f; --take) {
+        m |= f & (0u - f);
+        f &= f - 1u;
+    }
+    return m;
 }
 
 __device__ __forceinline__ void slab_free(const View &T, uint32_t idx)
 {
-    __hip_atomic_fetch_and(&T.bitmap[(size_t)(idx >> 11) * 64 + ((idx >> 5) & 63)],
-                           ~(1u << (idx & 31)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_and(bitmap_word(T, idx), ~(1u << (idx & 31)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -286,10 +522,10 @@ enum : uint32_t { kMsgFound = 1, kMsgEnd = 2, kMsgMove = 3, kMsgGrow = 4, kMsgSw
 
 // Per-wavefront LDS: cursor slab index, key and op kind of each op, and each op's outcome cell.
 struct WaveLds {
-    uint32_t u[64];
+    uint64_t p[64]; // each op's cursor slab (its address)
+    uint64_t msg[64];
     uint32_t key[64];
     uint32_t op[64];
-    uint64_t msg[64];
 };
 
 // The inputs of one chunk, one op per lane (lanes past the chunk's end hold no op).
@@ -333,7 +569,6 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
     const bool is31 = slot == 31;
     const uint32_t below = (1u << slot) - 1u; // slots of my half below mine
     const uint32_t hshift = lane & 32;
-    const uint64_t *lane_base = T.base + slot; // this lane's slot of slab 0
     const uint64_t i = base + lane;
     const bool in = lane < count;
     const uint32_t key = c.key, val = c.val, op = c.op;
@@ -355,13 +590,14 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
         todo = uniform64(todo);
         ++cnt.rounds;
         // ---- 1. load ----
-        L.u[lane] = ((todo >> lane) & 1) ? ((loc == kEmpty) ? bkt : T.B + loc) : 0u;
+        L.p[lane] = reinterpret_cast<uint64_t>(((todo >> lane) & 1) ? cursor_slab(T, loc, bkt)
+                                                                     : T.base);
         __builtin_amdgcn_wave_barrier();
         uint64_t pre[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const uint32_t u = L.u[2 * q + half];
-            pre[q] = load_slot<kCoherent>(lane_base + (size_t)u * 32);
+            const uint64_t *sp = reinterpret_cast<const uint64_t *>(L.p[2 * q + half]);
+            pre[q] = load_slot<kCoherent>(sp + slot);
         }
         // ---- 2. decide: the target lane of each op writes the op's outcome ----
 #pragma unroll
@@ -450,12 +686,27 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
             loc = payload;
         bool done = code == kMsgFound || code == kMsgEnd;
         uint64_t alloc_m = 0;
+        uint32_t claim_m = 0, claim_old = 0; // bitmap bits this lane claims for new tails
         if constexpr (K != kSearch) {
+            // An op at a full tail needs a new slab: it is claimed from the resident block now,
+            // so the bitmap atomic is in flight together with the swaps. One op per round and
+            // wavefront grows a list (the first in lane order); the others keep their cursor
+            // and re-read their tail next round, where they usually find it linked. So a
+            // wavefront never holds more than one slab it may have to give back, and slabs
+            // held by links about to be lost cannot make a pool under heavy contention look
+            // exhausted.
+            alloc_m = ballot(code == kMsgGrow);
+            alloc_m &= 0ull - alloc_m;
+            if (alloc_m) {
+                claim_m = claim_plan(al, lane, 1u);
+                if (claim_m)
+                    claim_old = __hip_atomic_fetch_or(&al.row[lane], claim_m, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            }
             bool won = false, lost = false;
             if (KO && code >= kMsgSwapIns) {
                 // key-only slab: 32-bit swaps on single entries
-                uint32_t *ent = reinterpret_cast<uint32_t *>(
-                    T.base + (size_t)((loc == kEmpty) ? bkt : T.B + loc) * 32);
+                uint32_t *ent = reinterpret_cast<uint32_t *>(cursor_slab(T, loc, bkt));
                 uint32_t e = tslot;
                 if (code == kMsgSwapRep) {
                     rs = 2u; // the key is already there: nothing to replace
@@ -509,7 +760,7 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
                 }
             } else if (code >= kMsgSwapIns) {
                 uint32_t cslot = tslot;
-                uint64_t *slab = T.base + (size_t)((loc == kEmpty) ? bkt : T.B + loc) * 32;
+                uint64_t *slab = cursor_slab(T, loc, bkt);
                 // a delete leaves a tombstone, or with duplicates an empty slot
                 const uint64_t desired = (code == kMsgSwapDel)
                                              ? (Dup ? kEmptyPair : kTombPair)
@@ -567,64 +818,84 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
             done = done || won;
             if (flags & kFlagCounters)
                 cnt.cas_lost += (uint32_t)__popcll(ballot(lost));
-            alloc_m = ballot(code == kMsgGrow);
         }
         todo &= ~ballot(done);
         if constexpr (K != kSearch) {
-            // ---- 4. allocate and link new tail slabs, one op at a time ----
-            while (alloc_m) {
-                const uint32_t j = ffs0(alloc_m);
-                alloc_m &= alloc_m - 1;
-                const uint32_t lj = rl(loc, j), bj = rl(bkt, j);
-                uint64_t *tail = T.base + (size_t)((lj == kEmpty) ? bj : T.B + lj) * 32;
-                const uint32_t idx = wave_alloc(T, al, lane);
-                if (idx == kEmpty) {
-                    raise_error(T, SH_ERR_POOL_EXHAUSTED, lane, 0);
-                    todo &= ~(1ull << j); // status stays 0
-                    continue;
-                }
-                ++cnt.allocs;
-                uint32_t *link = reinterpret_cast<uint32_t *>(tail + 31) + 1;
-                // Unique-key pair inserts put their pair in slot 0 of the new slab before linking
-                // it: the slab is private (and empty) until linked, so a winning link publishes
-                // the pair and the op is done in this round. Swaps are performed in memory; the
-                // link's new index passes through the prefill's result, so the link is issued
-                // only once the pair is in place, and no reader can follow it and miss the pair.
-                uint64_t *fresh = T.base + (size_t)(T.B + idx) * 32;
-                const uint64_t pair = ((uint64_t)rl(val, j) << 32) | rl(key, j);
-                uint32_t old = 0, put = 0;
-                if (lane == 0) {
-                    uint32_t desired = idx;
-                    if constexpr (kPrefill) {
-                        put = cas64(fresh, kEmptyPair, pair) == kEmptyPair;
-                        asm volatile("" : "+v"(desired) : "v"(put));
+            // ---- 4. allocate and link new tail slabs ----
+            if (alloc_m) {
+                // the slab claimed with the swaps, if the claim won its bit
+                const uint32_t got_m = claim_m & ~claim_old;
+                if (claim_m)
+                    al.word = claim_old | claim_m;
+                al.lost += (uint32_t)__popcll(ballot((claim_m & claim_old) != 0u));
+                uint32_t served;
+                uint32_t at = rotated_scan((uint32_t)__popc(got_m), lane, al.rot, &served);
+                uint32_t *claimed = reinterpret_cast<uint32_t *>(L.p); // scratch: loads are done
+                for (uint32_t w = got_m; w; w &= w - 1u)
+                    claimed[at++] = al.code + lane * 32 + (uint32_t)__builtin_ctz(w);
+                if (served)
+                    al.moves = 0;
+                __builtin_amdgcn_wave_barrier();
+                const bool grows = (alloc_m >> lane) & 1;
+                const uint32_t g = (uint32_t)__popcll(alloc_m & ((1ull << lane) - 1ull));
+                uint32_t idx = (grows && g < served) ? claimed[g] : kEmpty;
+                // if the claim could not serve it (the resident block's free bits were taken):
+                // the allocator proper, moving on through the blocks
+                uint64_t rest = alloc_m & ~ballot(idx != kEmpty);
+                while (rest) {
+                    const uint32_t j = ffs0(rest);
+                    rest &= rest - 1;
+                    const uint32_t x = wave_alloc(T, al, lane);
+                    if (x == kEmpty) {
+                        raise_error(T, SH_ERR_POOL_EXHAUSTED, lane, 0);
+                        todo &= ~(1ull << j); // status stays 0
+                        continue;
                     }
-                    old = cas32(link, kEmpty, desired);
+                    idx = wl(idx, j, x);
                 }
-                old = rl(old, 0);
-                put = rl(put, 0);
-                if (old == kEmpty) {
-                    if (put) {
-                        if (lane == j)
+                // The op links its slab: a swap of its tail's next index from empty to the new
+                // slab. On unique-key pair tables the op's pair goes into slot 0 of the new slab
+                // with a swap issued together with the link: a reader that follows the link
+                // before the pair lands sees an empty slot, which is the state before the
+                // insert, and if another insert fills slot 0 first this op takes the next round
+                // on the new slab. A link lost to another wavefront leaves the new slab private,
+                // so its pair went in; it is taken out again (a free slab must be empty) before
+                // the slab is returned, and the op follows the winner's slab.
+                const bool has = grows && idx != kEmpty;
+                bool linked_done = false, link_lost = false;
+                if (has) {
+                    uint64_t *tail = cursor_slab(T, loc, bkt);
+                    uint32_t *link = reinterpret_cast<uint32_t *>(tail + 31) + 1;
+                    uint64_t *fresh = pool_slab(T, idx);
+                    const uint64_t pair = ((uint64_t)val << 32) | key;
+                    uint64_t put = 0;
+                    if constexpr (kPrefill)
+                        put = cas64(fresh, kEmptyPair, pair);
+                    const uint32_t lold = cas32(link, kEmpty, idx);
+                    if (lold == kEmpty) {
+                        if (kPrefill && put == kEmptyPair) {
                             rs = 1u; // a new key, in slot 0 of the new tail
-                        todo &= ~(1ull << j);
+                            linked_done = true;
+                        } else {
+                            loc = idx;
+                        }
                     } else {
-                        loc = wl(loc, j, idx);
-                    }
-                } else {
-                    ++cnt.link_lost;
-                    if (lane == 0) {
-                        // another wavefront linked first; a free slab must be empty, so the
-                        // pair is taken out before the slab is returned
+                        link_lost = true;
                         uint32_t freed = idx;
-                        if (put) {
+                        if (kPrefill && put == kEmptyPair) {
                             const uint32_t back = cas64(fresh, pair, kEmptyPair) == pair;
                             asm volatile("" : "+v"(freed) : "v"(back));
                         }
                         slab_free(T, freed);
+                        loc = lold;
                     }
-                    loc = wl(loc, j, old);
                 }
+                if (flags & kFlagCounters) {
+                    const uint64_t hm = ballot(has);
+                    cnt.allocs += (uint32_t)__popcll(hm);
+                    cnt.link_lost += (uint32_t)__popcll(ballot(link_lost));
+                }
+                todo &= ~ballot(linked_done);
             }
         }
         // Every load of this round has been consumed; saying so lets the compiler issue the
@@ -650,6 +921,7 @@ __device__ __forceinline__ void flush_counters(const View &T, const Counters &cn
         atomicAdd(cs + 2, (unsigned long long)cnt.allocs);
         atomicAdd(cs + 3, (unsigned long long)cnt.link_lost);
         atomicAdd(cs + 4, (unsigned long long)al.total_moves);
+        atomicAdd(cs + 5, (unsigned long long)al.lost);
     }
 }
 
@@ -657,8 +929,12 @@ __device__ __forceinline__ void alloc_init(Alloc &al, uint32_t wave, uint32_t se
 {
     al.blk = kEmpty;
     al.word = 0;
+    al.row = nullptr;
+    al.code = 0;
+    al.nact = 0;
     al.moves = 0;
     al.total_moves = 0;
+    al.lost = 0;
     al.full = false;
     al.start = mix32(wave * 0x9E3779B9u + seq);
     al.rot = mix32(al.start) & 63u;
@@ -678,6 +954,8 @@ __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__re
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
     Alloc al;
     alloc_init(al, wave, seq);
+    if constexpr (K == kInsert || K == kMixed)
+        alloc_preload(T, al, lane_id());
     Counters cnt = {0, 0, 0, 0};
     const uint64_t nchunks = (n + C - 1) / C;
     for (uint64_t c = wave; c < nchunks; c += nwaves) {
@@ -709,28 +987,30 @@ __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ 
                                                        uint32_t C, uint32_t flags)
 {
     __shared__ WaveLds lds[kWavesPerBlock];
-    __shared__ uint32_t pre[kMaxBatches + 1];
-    __shared__ uint32_t part[kBlock];
+    // chunk counts in 64 bits (up to 4096 descriptors of up to 2^32 - 1 ops each); pre[] holds
+    // nb + 1 entries in the launch's dynamic LDS
+    extern __shared__ uint64_t pre[];
+    __shared__ uint64_t part[kBlock];
     const uint32_t tid = threadIdx.x;
     // exclusive prefix of chunk counts: each thread sums a contiguous segment, then the
     // segment sums are scanned across the block
     const uint32_t seg = (nb + kBlock - 1) / kBlock;
     const uint32_t s0 = tid * seg, s1 = (s0 + seg < nb) ? s0 + seg : nb;
-    uint32_t local = 0;
+    uint64_t local = 0;
     for (uint32_t d = s0; d < s1; ++d)
-        local += (desc[d].length + C - 1) / C;
+        local += ((uint64_t)desc[d].length + C - 1) / C;
     part[tid] = local;
     __syncthreads();
     for (uint32_t off = 1; off < kBlock; off <<= 1) {
-        const uint32_t v = (tid >= off) ? part[tid - off] : 0u;
+        const uint64_t v = (tid >= off) ? part[tid - off] : 0ull;
         __syncthreads();
         part[tid] += v;
         __syncthreads();
     }
-    uint32_t run = part[tid] - local; // exclusive start of this thread's segment
+    uint64_t run = part[tid] - local; // exclusive start of this thread's segment
     for (uint32_t d = s0; d < s1; ++d) {
         pre[d] = run;
-        run += (desc[d].length + C - 1) / C;
+        run += ((uint64_t)desc[d].length + C - 1) / C;
     }
     if (tid == kBlock - 1)
         pre[nb] = part[kBlock - 1];
@@ -739,12 +1019,12 @@ __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ 
     const uint32_t wl_ = tid >> 6;
     const uint32_t wave = blockIdx.x * kWavesPerBlock + wl_;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    const uint32_t total = pre[nb];
+    const uint64_t total = pre[nb];
     Alloc al;
     alloc_init(al, wave, seq);
     Counters cnt = {0, 0, 0, 0};
     uint32_t cur_t = kEmpty;
-    for (uint32_t c = wave; c < total; c += nwaves) {
+    for (uint64_t c = wave; c < total; c += nwaves) {
         // largest d with pre[d] <= c (descriptors with no ops have pre[d] == pre[d + 1])
         uint32_t lo = 0, hi = nb;
         while (hi - lo > 1) {
@@ -766,13 +1046,16 @@ __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ 
             cur_t = dd.table;
         }
         const View Tv = dir[cur_t];
-        const uint64_t first = (uint64_t)(c - pre[lo]) * C;
-        const uint64_t base = dd.offset + first;
-        uint64_t count = (dd.length - first < C) ? dd.length - first : C;
-        if (base >= n_ops)
-            count = 0; // range outside the op arrays: nothing is read or written
-        else if (count > n_ops - base)
-            count = n_ops - base;
+        alloc_preload(Tv, al, lane_id()); // once per table switch
+        // first < dd.length: chunk c is one of this descriptor's
+        const uint64_t first = (c - pre[lo]) * C;
+        uint64_t base = 0, count = 0; // a range outside the op arrays reads and writes nothing
+        if (dd.offset < n_ops && first < n_ops - dd.offset) {
+            base = dd.offset + first;
+            count = (dd.length - first < C) ? dd.length - first : C;
+            if (count > n_ops - base)
+                count = n_ops - base;
+        }
         run_chunk<kMixed, false, false, NQ>(
             Tv, al, cnt, lds[wl_],
             load_chunk<kMixed, false>(ops, keys, vals, base, (uint32_t)count), vout, sout, base,
@@ -788,8 +1071,7 @@ __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ 
 
 __device__ __forceinline__ bool bitmap_has(const View &T, uint32_t idx)
 {
-    const uint32_t w = T.bitmap[(size_t)(idx >> 11) * 64 + ((idx >> 5) & 63)];
-    return (w >> (idx & 31)) & 1u;
+    return (*bitmap_word(T, idx) >> (idx & 31)) & 1u;
 }
 
 template <bool KO>
@@ -894,11 +1176,12 @@ __global__ __launch_bounds__(kBlock) void walk_kernel(View T, uint32_t *__restri
                 break;
             if (E && !dup)
                 ++viol; // a slab with a successor must be full (with unique keys)
-            if (next >= T.pool_slabs || !bitmap_has(T, next) || ns > T.pool_slabs) {
+            if (!pool_in_range(T, next) || !bitmap_has(T, next) ||
+                ns > T.total_blocks * SH_BLOCK_SLABS) {
                 ++viol;
                 break;
             }
-            cur = T.pool + (size_t)next * 32;
+            cur = pool_slab(T, next);
         }
         if (counts && lane == 0) {
             counts[(size_t)3 * b] = nl;
@@ -948,13 +1231,14 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
         if (i >= count)
             continue; // an odd count leaves the last wavefront's upper half idle
         const uint32_t bkt = first + i;
-        uint32_t ru = bkt;         // unified index of the slab being read
-        uint32_t wu = bkt, ws = 0; // write position: slot ws of slab wu (kCap = wu is full)
-        uint32_t seen = 0, nxt = kEmpty;
+        uint64_t *rp = T.base + (size_t)bkt * 32; // the slab being read
+        uint64_t *wp = rp;                        // write position: slot ws of slab wp
+        uint32_t ws = 0, seen = 0, nxt = kEmpty;
+        const uint32_t limit = T.total_blocks * SH_BLOCK_SLABS;
         uint64_t w = 0;
         bool ok = true;
         for (;;) {
-            w = T.base[(size_t)ru * 32 + slot];
+            w = rp[slot];
             nxt = last_of_half((uint32_t)(w >> 32));
             const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
             const bool live = slot < 31 && lo != kEmpty && (!KO || lo != kTombKey);
@@ -963,34 +1247,34 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
             const uint32_t hm = (uint32_t)(ballot(live_hi) >> hshift);
             const uint32_t cnt = (uint32_t)(__popc(lm) + __popc(hm));
             if (cnt) {
-                // entries past the last slot of wu go to the slab after it, which the walk has
+                // entries past the last slot of wp go to the slab after it, which the walk has
                 // passed
-                uint32_t spill = 0;
+                uint64_t *sp = wp;
                 if (ws + cnt > kCap) {
-                    spill = (uint32_t)(T.base[(size_t)wu * 32 + 31] >> 32);
-                    if (spill >= T.pool_slabs) {
+                    const uint32_t spill = (uint32_t)(wp[31] >> 32);
+                    if (!pool_in_range(T, spill)) {
                         ok = false;
                         break;
                     }
+                    sp = pool_slab(T, spill);
                 }
                 const uint32_t pos = ws + (uint32_t)(__popc(lm & below) + __popc(hm & below));
-                const uint32_t du = (pos < kCap) ? wu : T.B + spill;
+                uint64_t *dp = (pos < kCap) ? wp : sp;
                 const uint32_t ds = (pos < kCap) ? pos : pos - kCap;
                 if constexpr (KO) {
-                    uint32_t *ent = reinterpret_cast<uint32_t *>(T.base);
                     const uint32_t pos2 = pos + (live ? 1u : 0u); // the high entry's position
-                    const uint32_t du2 = (pos2 < kCap) ? wu : T.B + spill;
+                    uint64_t *dp2 = (pos2 < kCap) ? wp : sp;
                     const uint32_t ds2 = (pos2 < kCap) ? pos2 : pos2 - kCap;
-                    if (live && (du != ru || ds != 2 * slot)) // entries in place stay
-                        ent[(size_t)du * 64 + ds] = lo;
-                    if (live_hi && (du2 != ru || ds2 != 2 * slot + 1))
-                        ent[(size_t)du2 * 64 + ds2] = hi;
+                    if (live && (dp != rp || ds != 2 * slot)) // entries in place stay
+                        reinterpret_cast<uint32_t *>(dp)[ds] = lo;
+                    if (live_hi && (dp2 != rp || ds2 != 2 * slot + 1))
+                        reinterpret_cast<uint32_t *>(dp2)[ds2] = hi;
                 } else {
-                    if (live && (du != ru || ds != slot)) // pairs in place stay
-                        T.base[(size_t)du * 32 + ds] = w;
+                    if (live && (dp != rp || ds != slot)) // pairs in place stay
+                        dp[ds] = w;
                 }
                 if (ws + cnt > kCap) {
-                    wu = T.B + spill;
+                    wp = sp;
                     ws = ws + cnt - kCap;
                 } else {
                     ws += cnt;
@@ -998,11 +1282,11 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
             }
             if (nxt == kEmpty)
                 break;
-            if (nxt >= T.pool_slabs || ++seen > T.pool_slabs) {
+            if (!pool_in_range(T, nxt) || ++seen > limit) {
                 ok = false;
                 break;
             }
-            ru = T.B + nxt;
+            rp = pool_slab(T, nxt);
         }
         if (!ok)
             continue;
@@ -1010,29 +1294,30 @@ __global__ __launch_bounds__(kBlock) void flush_kernel(View T, uint32_t first, u
         // then its slots after the write position are emptied and its next index cleared (word
         // 31 becomes all ones: auxiliary half and "no next"); words already so are not written
         uint32_t rest = nxt;
-        if (wu != ru)
-            rest = last_of_half((uint32_t)(T.base[(size_t)wu * 32 + slot] >> 32));
+        if (wp != rp)
+            rest = last_of_half((uint32_t)(wp[slot] >> 32));
         // the last slab read still holds its own words in w; an earlier tail is rewritten whole
         if constexpr (KO) {
-            uint32_t *ent = reinterpret_cast<uint32_t *>(T.base) + (size_t)wu * 64;
-            const bool same = wu == ru;
+            uint32_t *ent = reinterpret_cast<uint32_t *>(wp);
+            const bool same = wp == rp;
             if (2 * slot >= ws && !(same && (uint32_t)w == kEmpty))
                 ent[2 * slot] = kEmpty;
             if (2 * slot + 1 >= ws && !(same && (uint32_t)(w >> 32) == kEmpty))
                 ent[2 * slot + 1] = kEmpty;
         } else {
-            const bool keep = wu == ru && w == kEmptyPair;
+            const bool keep = wp == rp && w == kEmptyPair;
             if (slot >= ws && !keep)
-                T.base[(size_t)wu * 32 + slot] = kEmptyPair;
+                wp[slot] = kEmptyPair;
         }
         // the slabs that followed the tail go back to the pool, emptied
         uint32_t f = rest;
         seen = 0;
         while (f != kEmpty) {
-            if (f >= T.pool_slabs || ++seen > T.pool_slabs)
+            if (!pool_in_range(T, f) || ++seen > limit)
                 break;
-            const uint32_t nf = last_of_half((uint32_t)(T.pool[(size_t)f * 32 + slot] >> 32));
-            T.pool[(size_t)f * 32 + slot] = kEmptyPair;
+            uint64_t *fp = pool_slab(T, f);
+            const uint32_t nf = last_of_half((uint32_t)(fp[slot] >> 32));
+            fp[slot] = kEmptyPair;
             if (slot == 0)
                 slab_free(T, f);
             f = nf;
@@ -1096,7 +1381,9 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
                 lim = (base + op + 1 < n) ? offsets[base + op + 1] : vcap;
             }
             uint64_t w = pre[q];
-            uint32_t u = uu[op], found = 0, steps = 0;
+            uint64_t *up = T.base + (size_t)uu[op] * 32; // the slab being read
+            uint32_t found = 0, steps = 0;
+            const uint32_t limit = T.total_blocks * SH_BLOCK_SLABS;
             for (;;) {
                 const bool m = go && slot < 31 && (uint32_t)w == kq;
                 const bool m2 = KO && go && slot < 31 && (uint32_t)(w >> 32) == kq;
@@ -1107,14 +1394,13 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
                     bool ok = false, ok2 = false;
                     if constexpr (KO) {
                         // key-only entries: the key is the whole entry, so one swap decides
-                        uint32_t *e = reinterpret_cast<uint32_t *>(T.base + (size_t)u * 32) +
-                                      2 * slot;
+                        uint32_t *e = reinterpret_cast<uint32_t *>(up) + 2 * slot;
                         if (m)
                             ok = cas32(e, kq, (uint32_t)gone) == kq;
                         if (m2)
                             ok2 = cas32(e + 1, kq, (uint32_t)gone) == kq;
                     } else if (m) {
-                        uint64_t *p = T.base + (size_t)u * 32 + slot;
+                        uint64_t *p = up + slot;
                         uint64_t expect = w;
                         for (;;) {
                             const uint64_t old = cas64(p, expect, gone);
@@ -1144,12 +1430,12 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
                 found += hits;
                 const uint32_t nx = (uint32_t)__shfl((int)(uint32_t)(w >> 32),
                                                      (int)((lane & 32u) | 31u), 64);
-                go = go && nx != kEmpty && nx < T.pool_slabs && ++steps <= T.pool_slabs;
+                go = go && nx != kEmpty && pool_in_range(T, nx) && ++steps <= limit;
                 if (!ballot(go))
                     break;
                 if (go) {
-                    u = T.B + nx;
-                    w = load_slot<Del>(T.base + (size_t)u * 32 + slot);
+                    up = pool_slab(T, nx);
+                    w = load_slot<Del>(up + slot);
                 }
             }
             if (slot == 0 && op < count && counts)
@@ -1158,12 +1444,15 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
     }
 }
 
-// SlabAlloc on its own ("Dynamic memory allocation"): request i of n is served by lane i % 64 of
-// wavefront i / 64. The wavefront serves its lanes' requests one at a time from its resident
-// block, as the replace step does when a list needs a new slab. out[i] receives the pool index,
-// or kEmpty once the pool is exhausted.
+// SlabAlloc on its own ("Dynamic memory allocation"): requests 64 w .. 64 w + 63 of n belong to
+// wavefront w, which serves them together (wave_alloc_many) from its resident block. The
+// wavefronts partition the pool: wavefront w starts in block (w / 32) mod (blocks) at bitmap
+// word 2 (w mod 32), the 64 slabs its requests need when every slab is free, so wavefronts
+// sharing a block claim disjoint words and only a pool that is partly in use makes them hunt.
+// out[i] receives a pool index, or kEmpty once the pool is exhausted.
 __global__ __launch_bounds__(kBlock) void alloc_kernel(View T, uint64_t n,
-                                                       uint32_t *__restrict__ out, uint32_t seq)
+                                                       uint32_t *__restrict__ out, uint32_t seq,
+                                                       uint32_t flags)
 {
     const uint32_t lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
@@ -1173,18 +1462,16 @@ __global__ __launch_bounds__(kBlock) void alloc_kernel(View T, uint64_t n,
     const uint32_t cnt = (n - i0 < 64) ? (uint32_t)(n - i0) : 64u;
     Alloc al;
     alloc_init(al, (uint32_t)wave, seq);
-    uint32_t mine = kEmpty;
-    bool failed = false;
-    for (uint32_t j = 0; j < cnt; ++j) {
-        const uint32_t idx = wave_alloc(T, al, lane);
-        if (lane == j)
-            mine = idx;
-        failed = failed || idx == kEmpty;
-    }
-    if (failed)
+    al.start = (uint32_t)(wave / 32); // taken modulo the blocks in use
+    al.rot = (uint32_t)(wave % 32) * 2u;
+    const uint32_t got = wave_alloc_many(T, al, lane, cnt, out + i0);
+    if (got < cnt) {
         raise_error(T, SH_ERR_POOL_EXHAUSTED, lane, 0);
-    if (lane < cnt)
-        out[i0 + lane] = mine;
+        if (lane >= got && lane < cnt)
+            out[i0 + lane] = kEmpty;
+    }
+    if (flags & kFlagCounters)
+        flush_counters(T, Counters{0, 0, got, 0}, al, (uint32_t)wave);
 }
 
 // Deallocation: unset each slab's bit in its block's bitmap; entries outside the pool are skipped.
@@ -1194,18 +1481,24 @@ __global__ __launch_bounds__(kBlock) void free_kernel(View T, const uint32_t *__
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * kBlock) {
         const uint32_t f = idx[i];
-        if (f < T.pool_slabs)
+        if (pool_in_range(T, f))
             slab_free(T, f);
     }
 }
 
+// Set bits of the bitmap rows of every registered super block (words numbered over all of
+// them, allocator block order).
 __global__ __launch_bounds__(kBlock) void popcount_kernel(View T)
 {
-    const size_t nw = (size_t)T.nblk * 64;
+    const size_t nw = (size_t)T.total_blocks * 64;
     unsigned long long c = 0;
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < nw;
-         i += (size_t)gridDim.x * kBlock)
-        c += __popc(T.bitmap[i]);
+         i += (size_t)gridDim.x * kBlock) {
+        uint32_t *row;
+        uint32_t code;
+        block_ref(T, (uint32_t)(i >> 6), row, code);
+        c += __popc(row[i & 63]);
+    }
     // wave reduction via ballot-free shuffle-down
     for (int off = 32; off > 0; off >>= 1)
         c += __shfl_down(c, off, 64);
@@ -1246,13 +1539,23 @@ __global__ __launch_bounds__(kBlock) void init_kernel(uint4 *store, size_t hdr16
     }
 }
 
+// Registration of super block sb: its directory entry in the table header.
+__global__ void set_super_kernel(SuperDesc *dir, uint32_t sb, uint64_t *pool, uint32_t *bitmap,
+                                 uint32_t slabs, uint32_t first)
+{
+    if (threadIdx.x == 0)
+        dir[sb] = SuperDesc{pool, bitmap, slabs, first};
+}
+
 // Re-initialisation of a table in use. A free pool slab is always all ones: allocation hands
-// slabs out untouched, a lost link returns its slab untouched, FLUSH empties the slabs it frees,
-// and slabs given back through sh_free_slabs must be empty. So the storage comes back to what
-// the full initialisation writes by clearing the header, filling the base slabs with ones, and
-// filling only the pool slabs the bitmaps mark allocated before zeroing the bitmaps. Blocks
-// [0, fill_blocks) do the header and base slabs (16-byte stores, grid-stride over them); the
-// other blocks take one bitmap row (2048 pool slabs) per wavefront, grid-stride over the rows.
+// slabs out untouched, a lost link takes its pair out again before returning its slab, FLUSH
+// empties the slabs it frees, and slabs given back through sh_free_slabs must be empty. So the
+// storage comes back to what the full initialisation writes by clearing the header (all but the
+// super-block directory, which stays registered), filling the base slabs with ones, and filling
+// only the pool slabs the bitmaps mark allocated, in every super block, before zeroing the
+// bitmaps. Blocks [fill start, grid end) do the header and base slabs (16-byte stores,
+// grid-stride over them); the others take one bitmap row (2048 pool slabs) per wavefront,
+// grid-stride over the rows of all super blocks.
 // The bitmap walkers take the first blocks, so they are dispatched before the fill blocks
 // occupy the CUs; their dependent bitmap loads then overlap the fill instead of trailing it.
 __global__ __launch_bounds__(kBlock) void reset_kernel(View T, uint4 *store, size_t hdr16,
@@ -1261,8 +1564,11 @@ __global__ __launch_bounds__(kBlock) void reset_kernel(View T, uint4 *store, siz
     if (blockIdx.x >= pool_blocks) {
         const size_t total = hdr16 + base16;
         const uint32_t fill_blocks = gridDim.x - pool_blocks;
+        constexpr size_t kDir16 = kDirOffset / 16, kDirEnd16 = kGrownOffset / 16;
         for (size_t i = (size_t)(blockIdx.x - pool_blocks) * kBlock + threadIdx.x; i < total;
              i += (size_t)fill_blocks * kBlock) {
+            if (i >= kDir16 && i < kDirEnd16)
+                continue; // the super-block directory stays
             const uint32_t f = i >= hdr16 ? kEmpty : 0u;
             store[i] = make_uint4(f, f, f, f);
         }
@@ -1271,19 +1577,21 @@ __global__ __launch_bounds__(kBlock) void reset_kernel(View T, uint4 *store, siz
     const uint32_t lane = lane_id();
     const uint32_t wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const uint32_t nwaves = pool_blocks * kWavesPerBlock;
-    uint32_t *pool32 = reinterpret_cast<uint32_t *>(T.pool);
-    for (uint32_t r = wave; r < T.nblk; r += nwaves) {
-        uint32_t word = T.bitmap[(size_t)r * 64 + lane]; // slabs 2048 r + 32 lane + bit
+    // allocator blocks of every registered super block
+    for (uint32_t r = wave; r < T.total_blocks; r += nwaves) {
+        uint32_t *row, code;
+        block_ref(T, r, row, code);
+        uint32_t word = row[lane]; // slabs code + 32 lane + bit
         // the wavefront writes each allocated slab whole: 64 lanes x 4 bytes
         for (uint64_t m = ballot(word != 0); m; m = ballot(word != 0)) {
             const uint32_t j = ffs0(m);
             const uint32_t bit = (uint32_t)__builtin_ctz(rl(word, j));
-            const size_t slab = (size_t)r * SH_BLOCK_SLABS + j * 32 + bit;
-            pool32[slab * 64 + lane] = kEmpty;
+            uint32_t *sl = reinterpret_cast<uint32_t *>(pool_slab(T, code + j * 32 + bit));
+            sl[lane] = kEmpty;
             if (lane == j)
                 word &= word - 1u; // that slab is done
         }
-        T.bitmap[(size_t)r * 64 + lane] = 0u;
+        row[lane] = 0u;
     }
 }
 
@@ -1303,6 +1611,9 @@ struct sh_table {
     uint32_t flags;        // SH_LAUNCH_* bits
     int num_cu;
     int embedded; // owned by a multi-table object
+    struct sh_multi *owner; // that object, and this table's index in it
+    uint32_t index;
+    uint64_t super_slabs; // slabs of the super blocks registered beyond super block 0
 };
 
 struct sh_multi {
@@ -1329,7 +1640,8 @@ struct Layout {
 
 bool layout_of(const sh_params_t *p, Layout *L)
 {
-    if (!p || p->num_buckets == 0 || p->pool_slabs % SH_BLOCK_SLABS != 0 || p->hash_a == 0 ||
+    if (!p || p->num_buckets == 0 || p->pool_slabs % SH_BLOCK_SLABS != 0 ||
+        p->pool_slabs > kMaxSuperSlabs || p->hash_a == 0 ||
         p->hash_a >= kPrime || p->hash_b >= kPrime ||
         (uint64_t)p->num_buckets + p->pool_slabs >= 0xFFFFFFFFull ||
         (p->flags & ~(uint32_t)(SH_TABLE_DUPLICATES | SH_TABLE_KEYS_ONLY)) != 0)
@@ -1399,25 +1711,32 @@ uint32_t ops_per_wave_for(const sh_table *t, uint64_t n, int kind)
 // come from several host threads.
 uint32_t next_seq(uint32_t *seq) { return __atomic_fetch_add(seq, 1u, __ATOMIC_RELAXED); }
 
-// Wavefronts of kernel `fn` that fit on one compute unit at once (its registers and LDS), from
-// the occupancy API, cached per kernel (one GPU model per process); 64 (no limit) if the query
-// fails, whose error is then cleared so that the launch check after it does not report it.
-uint32_t resident_waves_per_cu(const void *fn)
+// Wavefronts of kernel `fn` that fit on one compute unit at once (its registers and LDS, with
+// `dyn_lds` bytes of dynamic LDS per block), from the occupancy API, cached per kernel and LDS
+// size (one GPU model per process); 64 (no limit) if the query fails, whose error is then
+// cleared so that the launch check after it does not report it.
+uint32_t resident_waves_per_cu(const void *fn, size_t dyn_lds = 0)
 {
+    struct Entry {
+        const void *fn;
+        size_t lds;
+        uint32_t waves;
+    };
     static std::mutex mu;
-    static std::vector<std::pair<const void *, uint32_t>> cache;
+    static std::vector<Entry> cache;
     std::lock_guard<std::mutex> g(mu);
     for (const auto &e : cache)
-        if (e.first == fn)
-            return e.second;
+        if (e.fn == fn && e.lds == dyn_lds)
+            return e.waves;
     int nb = 0;
     uint32_t w = 64;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) == hipSuccess && nb > 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, dyn_lds) == hipSuccess &&
+        nb > 0)
         w = (uint32_t)nb * kWavesPerBlock;
     else
         (void)hipGetLastError();
     try {
-        cache.emplace_back(fn, w);
+        cache.push_back(Entry{fn, dyn_lds, w});
     } catch (...) {
         // not cached: the next launch asks again
     }
@@ -1427,12 +1746,19 @@ uint32_t resident_waves_per_cu(const void *fn)
 // Waves per CU of a persistent launch of `fn`: the caller's explicit choice (set > 0) as given;
 // else the default, lowered to what fits at once, so no wavefront waits for another to finish
 // its whole share.
-uint32_t launch_wpc(uint32_t set, uint32_t dflt, const void *fn)
+uint32_t launch_wpc(uint32_t set, uint32_t dflt, const void *fn, size_t dyn_lds = 0)
 {
     if (set)
         return set;
-    const uint32_t r = resident_waves_per_cu(fn);
+    const uint32_t r = resident_waves_per_cu(fn, dyn_lds);
     return r < dflt ? r : dflt;
+}
+
+// Dynamic LDS of a batched launch over nb descriptors: their 64-bit chunk prefix, rounded up
+// to a multiple of 64 descriptors so that few distinct sizes reach the occupancy cache.
+size_t multi_lds_bytes(uint32_t nb)
+{
+    return (size_t)(((nb + 1 + 63) / 64) * 64) * sizeof(uint64_t);
 }
 
 uint32_t grid_for(const sh_table *t, uint64_t n, uint32_t C, uint32_t wpc)
@@ -1550,8 +1876,8 @@ sh_status_t walk(sh_table *t, uint32_t *dbkt, uint32_t *dkey, uint32_t *dval, ui
                            dbkt, dkey, dval, cap, counts, emit);
     if (check_launch() != SH_OK)
         return SH_EHIP;
-    if (t->v.nblk) {
-        uint32_t pb = (uint32_t)(((size_t)t->v.nblk * 64 + kBlock - 1) / kBlock);
+    if (t->v.total_blocks) {
+        uint32_t pb = (uint32_t)(((size_t)t->v.total_blocks * 64 + kBlock - 1) / kBlock);
         if (pb > (uint32_t)t->num_cu * 4)
             pb = (uint32_t)t->num_cu * 4;
         hipLaunchKernelGGL(popcount_kernel, dim3(pb), dim3(kBlock), 0, S(stream), t->v);
@@ -1601,7 +1927,12 @@ void bind_table(sh_table *t, const sh_params_t *p, char *storage, size_t bytes, 
     t->v.b = p->hash_b;
     t->v.pool_slabs = p->pool_slabs;
     t->v.nblk = p->pool_slabs / SH_BLOCK_SLABS;
+    t->v.dir = reinterpret_cast<const SuperDesc *>(storage + kDirOffset);
+    t->v.grown = reinterpret_cast<uint32_t *>(storage + kGrownOffset);
+    t->v.nsuper = 1;
+    t->v.total_blocks = t->v.nblk;
     t->v.mode = p->flags & (SH_TABLE_DUPLICATES | SH_TABLE_KEYS_ONLY);
+    t->super_slabs = 0;
 }
 
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1655,12 +1986,14 @@ sh_status_t launch_multi_raw(const View *d_dir, uint32_t T, const sh_batch_desc_
     const MultiFn fn = C == 64 ? multi_kernel<32>
                                : C == 32 ? multi_kernel<16>
                                          : C == 16 ? multi_kernel<8> : multi_kernel<4>;
-    uint64_t w = (uint64_t)num_cu *
-                 launch_wpc(wpc, kDefaultWavesPerCU, reinterpret_cast<const void *>(fn));
+    uint64_t w = (uint64_t)num_cu * launch_wpc(wpc, kDefaultWavesPerCU,
+                                               reinterpret_cast<const void *>(fn),
+                                               multi_lds_bytes(nb));
     const uint64_t chunks = (work_ops + C - 1) / C + nb; // at most one partial chunk each
     if (w > chunks)
         w = chunks;
-    hipLaunchKernelGGL(fn, dim3(blocks_for(w)), dim3(kBlock), 0, stream, d_dir, T, d_desc, nb,
+    hipLaunchKernelGGL(fn, dim3(blocks_for(w)), dim3(kBlock), multi_lds_bytes(nb), stream,
+                       d_dir, T, d_desc, nb,
                        n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
     return check_launch();
 }
@@ -1720,8 +2053,8 @@ sh_status_t sh_reset(sh_table_t *t, void *stream)
     const size_t cap = (size_t)t->num_cu * 8;
     if (fill > cap)
         fill = cap;
-    // one wavefront per bitmap row, at most the pool's rows
-    const size_t rows = t->v.nblk;
+    // one wavefront per bitmap row, at most the rows of every super block
+    const size_t rows = t->v.total_blocks;
     size_t pool_blocks = (rows + kWavesPerBlock - 1) / kWavesPerBlock;
     if (pool_blocks > cap)
         pool_blocks = cap;
@@ -1729,6 +2062,57 @@ sh_status_t sh_reset(sh_table_t *t, void *stream)
                        S(stream), t->v, reinterpret_cast<uint4 *>(t->storage), hdr16, base16,
                        (uint32_t)pool_blocks);
     return check_launch();
+}
+
+size_t sh_super_block_bytes(uint32_t slabs)
+{
+    if (slabs == 0 || slabs % SH_BLOCK_SLABS != 0 || slabs > kMaxSuperSlabs)
+        return 0;
+    return (size_t)slabs * SH_SLAB_BYTES + (size_t)(slabs / SH_BLOCK_SLABS) * 256;
+}
+
+sh_status_t sh_add_super_block(sh_table_t *t, void *d_mem, size_t bytes, void *stream)
+{
+    if (!t || !d_mem || (reinterpret_cast<uintptr_t>(d_mem) & 255u) ||
+        t->v.nsuper >= kMaxSupers)
+        return SH_EINVAL;
+    // the most slabs (a multiple of a block, at most kMaxSuperSlabs) whose slabs and bitmap
+    // rows fit in `bytes`
+    const size_t per_block = (size_t)SH_BLOCK_SLABS * SH_SLAB_BYTES + 256;
+    uint64_t blocks = bytes / per_block;
+    if (blocks > kMaxSuperSlabs / SH_BLOCK_SLABS)
+        blocks = kMaxSuperSlabs / SH_BLOCK_SLABS;
+    if (blocks == 0 || (uint64_t)t->v.total_blocks + blocks > (1ull << 31))
+        return SH_EINVAL;
+    const uint32_t slabs = (uint32_t)(blocks * SH_BLOCK_SLABS);
+    char *mem = static_cast<char *>(d_mem);
+    uint64_t *pool = reinterpret_cast<uint64_t *>(mem);
+    uint32_t *bitmap = reinterpret_cast<uint32_t *>(mem + (size_t)slabs * SH_SLAB_BYTES);
+    // slabs all ones (empty), bitmap rows zero (free), then the directory entry
+    const size_t ones16 = (size_t)slabs * SH_SLAB_BYTES / 16, zeros16 = blocks * 256 / 16;
+    size_t nb = (ones16 + zeros16 + kBlock - 1) / kBlock;
+    if (nb > (size_t)t->num_cu * 8)
+        nb = (size_t)t->num_cu * 8;
+    const uint32_t sb = t->v.nsuper;
+    hipLaunchKernelGGL(init_kernel, dim3((uint32_t)nb), dim3(kBlock), 0, S(stream),
+                       reinterpret_cast<uint4 *>(mem), (size_t)0, ones16, zeros16);
+    hipLaunchKernelGGL(set_super_kernel, dim3(1), dim3(64), 0, S(stream),
+                       const_cast<SuperDesc *>(t->v.dir), sb, pool, bitmap, slabs,
+                       t->v.total_blocks);
+    if (check_launch() != SH_OK)
+        return SH_EHIP;
+    t->v.nsuper = sb + 1;
+    t->v.total_blocks += (uint32_t)blocks;
+    t->super_slabs += slabs;
+    if (t->owner) {
+        // the batched kernel reads the tables' views from the multi-table directory
+        sh_multi *m = t->owner;
+        m->h_dir[t->index] = t->v;
+        if (hipMemcpyAsync(m->d_dir + t->index, m->h_dir + t->index, sizeof(View),
+                           hipMemcpyHostToDevice, S(stream)) != hipSuccess)
+            return SH_EHIP;
+    }
+    return SH_OK;
 }
 
 sh_status_t sh_flush(sh_table_t *t, uint32_t first_bucket, uint32_t num_buckets, void *stream)
@@ -1814,7 +2198,7 @@ sh_status_t sh_alloc_slabs(sh_table_t *t, uint64_t n, uint32_t *d_out, void *str
         return SH_OK;
     const uint64_t blocks = (n + kBlock - 1) / kBlock; // one request per lane
     hipLaunchKernelGGL(alloc_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, S(stream), t->v, n,
-                       d_out, next_seq(&t->seq));
+                       d_out, next_seq(&t->seq), t->flags);
     return check_launch();
 }
 
@@ -1931,16 +2315,16 @@ sh_status_t sh_stats(sh_table_t *t, sh_stats_t *h_out, void *stream)
             hipSuccess ||
         hipStreamSynchronize(S(stream)) != hipSuccess)
         return SH_EHIP;
-    unsigned long long sum[5] = {0, 0, 0, 0, 0};
+    unsigned long long sum[6] = {0, 0, 0, 0, 0, 0};
     for (uint32_t k = 0; k < kCounterSlots; ++k)
-        for (int f = 0; f < 5; ++f)
+        for (int f = 0; f < 6; ++f)
             sum[f] += cs[k * 8 + f];
     memset(h_out, 0, sizeof(*h_out));
     h_out->live = h.live;
     h_out->tombstones = h.tomb;
     h_out->slabs_total = h.slabs;
     h_out->pool_allocated = h.pool_alloc;
-    h_out->pool_capacity = t->p.pool_slabs;
+    h_out->pool_capacity = t->p.pool_slabs + t->super_slabs;
     h_out->error_word = h.err;
     h_out->violations = h.violations;
     h_out->num_buckets = t->p.num_buckets;
@@ -1952,6 +2336,7 @@ sh_status_t sh_stats(sh_table_t *t, sh_stats_t *h_out, void *stream)
     h_out->allocs = sum[2];
     h_out->link_lost = sum[3];
     h_out->block_moves = sum[4];
+    h_out->alloc_lost = sum[5];
     return SH_OK;
 }
 
@@ -2009,6 +2394,8 @@ sh_status_t sh_multi_create(uint32_t T, const sh_params_t *h_params, void *d_sto
         layout_of(&h_params[t], &L);
         bind_table(&m->tables[t], &h_params[t], m->storage + offs[t], L.total, ncu);
         m->tables[t].embedded = 1;
+        m->tables[t].owner = m;
+        m->tables[t].index = t;
         m->h_dir[t] = m->tables[t].v;
         s = launch_init(&m->tables[t], stream);
     }
@@ -2134,6 +2521,45 @@ sh_status_t sh_multi_graph(sh_multi_t *m, const sh_batch_desc_t *d_desc, uint32_
             (void)hipGraphDestroy(g->graph);
         free(g);
         return s;
+    }
+    *out = g;
+    return SH_OK;
+}
+
+sh_status_t sh_capture_begin(void *stream)
+{
+    if (!stream)
+        return SH_EINVAL; // the NULL stream cannot be captured
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(S(stream), &st) != hipSuccess)
+        return SH_EHIP;
+    if (st != hipStreamCaptureStatusNone)
+        return SH_EINVAL;
+    return hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal) == hipSuccess
+               ? SH_OK
+               : SH_EHIP;
+}
+
+sh_status_t sh_capture_end(void *stream, sh_graph_t **out)
+{
+    if (!stream || !out)
+        return SH_EINVAL;
+    hipGraph_t graph = nullptr;
+    if (hipStreamEndCapture(S(stream), &graph) != hipSuccess || !graph) {
+        if (graph)
+            (void)hipGraphDestroy(graph); // best effort on the error path
+        return SH_EHIP;
+    }
+    sh_graph *g = static_cast<sh_graph *>(calloc(1, sizeof(sh_graph)));
+    if (!g) {
+        (void)hipGraphDestroy(graph);
+        return SH_ENOMEM;
+    }
+    g->graph = graph;
+    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        free(g);
+        return SH_EHIP;
     }
     *out = g;
     return SH_OK;
@@ -2476,7 +2902,8 @@ sh_status_t sh_server_submit(sh_server_t *s, const sh_request_t *req, uint64_t *
     if (s->stop)
         return SH_EINVAL;
     const int64_t avail =
-        (int64_t)s->t->p.pool_slabs - s->allocated - (int64_t)s->cfg.reserve_slabs;
+        (int64_t)(s->t->p.pool_slabs + s->t->super_slabs) - s->allocated -
+        (int64_t)s->cfg.reserve_slabs;
     if ((int64_t)req->inserts > avail)
         return s->unfinished == 0 ? SH_ENOMEM : SH_EBUSY;
     if (s->unfinished >= s->cfg.max_requests || (int64_t)req->inserts > avail - s->reserved)

@@ -58,7 +58,8 @@ class ShStats(ctypes.Structure):
                 ("hash_a", ctypes.c_uint32), ("hash_b", ctypes.c_uint32),
                 ("hash_p", ctypes.c_uint32), ("rounds", ctypes.c_uint64),
                 ("cas_lost", ctypes.c_uint64), ("allocs", ctypes.c_uint64),
-                ("link_lost", ctypes.c_uint64), ("block_moves", ctypes.c_uint64)]
+                ("link_lost", ctypes.c_uint64), ("block_moves", ctypes.c_uint64),
+                ("alloc_lost", ctypes.c_uint64)]
 
 
 class ShServerCfg(ctypes.Structure):
@@ -86,6 +87,8 @@ _SIGS = {
     "sh_flush": ([_P, _U32, _U32, _P], ctypes.c_int),
     "sh_alloc_slabs": ([_P, _U64, _P, _P], ctypes.c_int),
     "sh_search_all": ([_P, _P, _U64, _P, _P, _P, _U64, _P], ctypes.c_int),
+    "sh_super_block_bytes": ([_U32], _SZ),
+    "sh_add_super_block": ([_P, _P, _SZ, _P], ctypes.c_int),
     "sh_delete_all": ([_P, _P, _U64, _P, _P], ctypes.c_int),
     "sh_free_slabs": ([_P, _P, _U64, _P], ctypes.c_int),
     "sh_destroy": ([_P], ctypes.c_int),
@@ -113,6 +116,8 @@ _SIGS = {
     "sh_server_replay": ([_P, _P, _P, _U64, _P, _P], ctypes.c_int),
     "sh_server_stop": ([_P], ctypes.c_int),
     "sh_clock_ns": ([], _U64),
+    "sh_capture_begin": ([_P], ctypes.c_int),
+    "sh_capture_end": ([_P, _P], ctypes.c_int),
     "sh_graph_launch": ([_P, _P], ctypes.c_int),
     "sh_graph_destroy": ([_P], ctypes.c_int),
     "sh_multi_destroy": ([_P], ctypes.c_int),
@@ -201,6 +206,17 @@ def sh_reset(t, stream=None) -> None:
 
 def sh_flush(t, first_bucket: int, num_buckets: int, stream=None) -> None:
     _check("sh_flush", lib().sh_flush(t, int(first_bucket), int(num_buckets), _stream(stream)))
+
+
+def sh_super_block_bytes(slabs: int) -> int:
+    return int(lib().sh_super_block_bytes(int(slabs)))
+
+
+def sh_add_super_block(t, mem: torch.Tensor, stream=None) -> None:
+    if not isinstance(mem, torch.Tensor) or not mem.is_cuda or not mem.is_contiguous():
+        raise ValueError("mem must be a contiguous CUDA tensor")
+    _check("sh_add_super_block", lib().sh_add_super_block(
+        t, mem.data_ptr(), mem.numel() * mem.element_size(), _stream(stream)))
 
 
 def sh_search_all(t, keys: torch.Tensor, counts: torch.Tensor, offsets=None, vals=None,
@@ -378,6 +394,18 @@ def sh_multi_graph(m, desc, nb, ops, keys, vals_in, vals_out, status) -> ctypes.
     return out
 
 
+def sh_capture_begin(stream) -> None:
+    """Start capturing the work later calls enqueue on `stream` (a non-default stream)."""
+    _check("sh_capture_begin", lib().sh_capture_begin(_stream(stream)))
+
+
+def sh_capture_end(stream) -> ctypes.c_void_p:
+    """Finish the capture on `stream`; returns the graph (replay with sh_graph_launch)."""
+    out = ctypes.c_void_p()
+    _check("sh_capture_end", lib().sh_capture_end(_stream(stream), ctypes.byref(out)))
+    return out
+
+
 def sh_graph_launch(g, stream=None) -> None:
     _check("sh_graph_launch", lib().sh_graph_launch(g, _stream(stream)))
 
@@ -498,6 +526,7 @@ class SlabHash:
                                | (SH_TABLE_KEYS_ONLY if keys_only else 0))
         self.device = device
         self.owner = owner
+        self.supers = []  # device memory of registered super blocks, in order
         if handle is not None:
             self.storage = None
             self.handle = handle
@@ -521,6 +550,17 @@ class SlabHash:
     def num_buckets(self) -> int:
         """Bucket count B."""
         return self.params.num_buckets
+
+    def add_super_block(self, slabs: int, stream=None) -> torch.Tensor:
+        """Register a further super block of `slabs` slabs (a multiple of 2048) in new device
+        memory, which this object keeps; returns that memory."""
+        nbytes = sh_super_block_bytes(slabs)
+        if nbytes == 0:
+            raise ValueError("slabs must be a positive multiple of 2048, at most 2^27 - 2048")
+        mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        sh_add_super_block(self.handle, mem, stream)
+        self.supers.append(mem)
+        return mem
 
     def reset(self, stream=None):
         """Re-initialise the table in place: every slot and next index empty, every pool slab free

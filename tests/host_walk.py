@@ -25,17 +25,32 @@ EMPTY64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 TOMB64 = np.uint64(0x00000000FFFFFFFF)
 
 
-def raw_parts(t):
-    """(base [B,32] u64, pool [P,32] u64, bitmap [P/2048, 64] u32) of a table with its own
-    storage, copied from the device."""
+SUPER_SHIFT = 27
+
+
+def super_slabs(nbytes):
+    """Slabs of a super block registered with `nbytes` bytes: the most whole blocks whose slabs
+    and bitmap rows fit, at most 2^27 - 2048 slabs."""
+    return min(nbytes // (BLOCK * SLAB + 256), (1 << SUPER_SHIFT) // BLOCK - 1) * BLOCK
+
+
+def raw_parts(t, supers=()):
+    """(base [B,32] u64, pools, bitmaps) of a table with its own storage, copied from the device:
+    pools[s] [P_s, 32] u64 and bitmaps[s] [P_s/2048, 64] u32 for super block s (0 = the table's
+    own pool, then the device tensors in `supers` in registration order)."""
     B, P = int(t.params.num_buckets), int(t.params.pool_slabs)
     raw = t.storage.cpu().numpy()
     o_pool = HEADER + B * SLAB
     o_bm = o_pool + P * SLAB
     base = raw[HEADER:o_pool].view(np.uint64).reshape(B, 32)
-    pool = raw[o_pool:o_bm].view(np.uint64).reshape(P, 32)
-    bm = raw[o_bm:o_bm + (P // BLOCK) * 256].view(np.uint32).reshape(-1, 64)
-    return base, pool, bm
+    pools = [raw[o_pool:o_bm].view(np.uint64).reshape(P, 32)]
+    bms = [raw[o_bm:o_bm + (P // BLOCK) * 256].view(np.uint32).reshape(-1, 64)]
+    for mem in supers:
+        r = mem.cpu().numpy()
+        n = super_slabs(r.size)
+        pools.append(r[:n * SLAB].view(np.uint64).reshape(n, 32))
+        bms.append(r[n * SLAB:n * SLAB + (n // BLOCK) * 256].view(np.uint32).reshape(-1, 64))
+    return base, pools, bms
 
 
 def _counts(rows, keys_only):
@@ -54,9 +69,28 @@ def _counts(rows, keys_only):
     return live.astype(np.int64), tomb.astype(np.int64)
 
 
-def check_structure(t, keys_only=False):
-    base, pool, bm = raw_parts(t)
-    B, P = base.shape[0], pool.shape[0]
+def check_structure(t, keys_only=False, supers=None):
+    """Pool slab addresses carry their super block in the top 5 bits (0 = the table's own
+    pool); `supers` defaults to the table's registered super blocks (t.supers)."""
+    if supers is None:
+        supers = getattr(t, "supers", [])
+    base, pools, bms = raw_parts(t, supers)
+    B = base.shape[0]
+    sizes = np.array([p.shape[0] for p in pools], np.int64)
+    first = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    pool = np.concatenate(pools) if len(pools) > 1 else pools[0]
+    P = pool.shape[0]
+
+    def flat(addr):
+        """Global row of each pool address (-1 if it names no registered slab)."""
+        sb = (addr >> np.uint32(SUPER_SHIFT)).astype(np.int64)
+        i = (addr & np.uint32((1 << SUPER_SHIFT) - 1)).astype(np.int64)
+        ok = (sb < sizes.size)
+        ok[ok] &= i[ok] < sizes[sb[ok]]
+        out = np.full(addr.shape, -1, np.int64)
+        out[ok] = first[sb[ok]] + i[ok]
+        return out
+
     live, tomb = _counts(base, keys_only)
     slabs = np.ones(B, np.int64)
     refs = np.zeros(P, np.int64)
@@ -67,9 +101,9 @@ def check_structure(t, keys_only=False):
         on = nxt != EMPTY32
         if not on.any():
             break
-        idx = nxt[on].astype(np.int64)
-        assert (idx < P).all(), "1: a next index points outside the pool (bucket %d)" % \
-            int(owner[on][idx >= P][0])
+        idx = flat(nxt[on])
+        assert (idx >= 0).all(), "1: a next index points outside the pool (bucket %d)" % \
+            int(owner[on][idx < 0][0])
         depth += 1
         assert depth <= P, "1: a slab list does not end"
         np.add.at(refs, idx, 1)
@@ -81,8 +115,10 @@ def check_structure(t, keys_only=False):
         np.add.at(slabs, b_on, 1)
         owner = b_on
         nxt = (rows[:, 31] >> np.uint64(32)).astype(np.uint32)
-    bits = np.unpackbits(bm.reshape(-1).view(np.uint8), bitorder="little").astype(bool)[:P]
-    assert refs.max(initial=0) <= 1, "2: pool slab %d is referenced %d times" % (
+    bits = np.concatenate([
+        np.unpackbits(bm.reshape(-1).view(np.uint8), bitorder="little").astype(bool)[:n]
+        for bm, n in zip(bms, sizes)])
+    assert refs.max(initial=0) <= 1, "2: pool slab row %d is referenced %d times" % (
         int(refs.argmax()), int(refs.max()))
     ref = refs == 1
     bad = np.flatnonzero(ref & ~bits)

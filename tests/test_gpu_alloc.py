@@ -91,3 +91,26 @@ def test_table_after_alloc_and_release(oracle_mod):
     assert bool((t.insert(S.to_dev(keys), S.to_dev(vals)) == 1).all())
     o.replace(keys, vals)
     assert_same_table(t, o)
+
+
+def test_whole_pool_and_counters():
+    """A pool exactly the size of the request count: the wavefronts' starting words partition
+    it, every slab is handed out once, and the counters account for every allocation."""
+    say("case: 2^18 allocations from a pool of 2^18")
+    n = 1 << 18
+    t = S.SlabHash(1, n, 19, 23)
+    t.set_launch(0, 0, S.SH_LAUNCH_COUNTERS)
+    a = alloc(t, n)
+    assert (a != EMPTY).all() and np.unique(a).size == n
+    st = t.stats()
+    assert st["allocs"] == n and st["pool_allocated"] == n and st["error_word"] == 0
+    # half of them back, in a scattered pattern; then the same number again: the wavefronts
+    # now hunt through partly used words and blocks
+    rng = W.SplitMix64(7)
+    gone = a[rng.permutation(n)[: n // 2]]
+    S.sh_free_slabs(t.handle, S.to_dev(gone))
+    b = alloc(t, n // 2)
+    assert (b != EMPTY).all() and np.unique(b).size == b.size
+    assert np.intersect1d(b, np.setdiff1d(a, gone)).size == 0
+    assert t.stats()["pool_allocated"] == n
+    assert (alloc(t, 64) == EMPTY).all()

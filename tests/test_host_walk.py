@@ -102,3 +102,42 @@ def test_key_only_counts():
     t.base()[0, 1] = np.uint64((0xFFFFFFFF << 32) | 0xFFFFFFFE)  # a deleted key, then empty
     live, tomb, slabs = HW.check_structure(t, keys_only=True)
     assert live.tolist() == [2] and tomb.tolist() == [1] and slabs.tolist() == [1]
+
+
+def test_super_block_size_matches_the_library():
+    """The reader's super-block geometry is the one the header states, and the library's byte
+    count for S slabs (sh_super_block_bytes) gives back S slabs."""
+    from paper_1710_11246_amd import slabhash as S
+    for slabs in (2048, 4096, 3 * 2048, 1 << 20):
+        nb = S.sh_super_block_bytes(slabs)
+        assert nb == slabs * 256 + slabs // 2048 * 256
+        assert HW.super_slabs(nb) == slabs
+        assert HW.super_slabs(nb - 1) == slabs - 2048
+    assert S.sh_super_block_bytes(0) == 0 and S.sh_super_block_bytes(2047) == 0
+    assert S.sh_super_block_bytes((1 << 27) - 2048) > 0 and S.sh_super_block_bytes(1 << 27) == 0
+
+
+def test_lists_through_super_blocks():
+    """A list whose second slab is in super block 1 (address 1 << 27 | 3) and third in super
+    block 2 is followed, counted and checked like any other."""
+    t = sample()
+    s1 = np.zeros(HW.SLAB * 2048 + 256, np.uint8)
+    s2 = np.zeros(HW.SLAB * 2048 + 256, np.uint8)
+    p1 = s1[:2048 * 256].view(np.uint64).reshape(2048, 32)
+    p2 = s2[:2048 * 256].view(np.uint64).reshape(2048, 32)
+    p1[:] = E64
+    p2[:] = E64
+    b1 = s1[2048 * 256:].view(np.uint32)
+    b2 = s2[2048 * 256:].view(np.uint32)
+    t.link(t.base()[1], (1 << 27) | 3)
+    p1[3, 0] = pair(50, 5)
+    t.link(p1[3], (2 << 27) | 40)
+    p2[40, 0] = pair(60, 6)
+    b1[0] |= np.uint32(1 << 3)
+    b2[1] |= np.uint32(1 << 8)
+    supers = [torch.from_numpy(s1), torch.from_numpy(s2)]
+    live, tomb, slabs = HW.check_structure(t, supers=supers)
+    assert live.tolist() == [33, 4, 0] and slabs.tolist() == [2, 3, 1]
+    b2[1] = 0
+    with pytest.raises(AssertionError, match="3:"):
+        HW.check_structure(t, supers=supers)
