@@ -210,11 +210,36 @@ def test_planted_mistakes_are_caught(plant, case):
     pytest.fail("planted mistake %s not caught" % plant)
 
 
+def growth_race_case(M, sd, traces=None):
+    """One full slab and eight fresh keys inserted by four wavefronts at once: every one of
+    them meets a full tail, so the lists grow under contention."""
+    seq = SeqTable(1, M, False)
+    for k in range(M):
+        seq.insert(k, 1000 + k)
+    mem = WM.Memory(1, 16, M)
+    load(mem, seq)
+    ops = [WM.Op("insert", 100 + i, 2000 + i) for i in range(8)]
+    tr = WM.run_schedule(mem, chunks_of(ops, [2, 2, 2, 2]), False, sd)
+    if traces is not None:
+        traces.extend(tr)
+    assert all(op.status == 1 for op in ops)
+    for op in ops:
+        seq.insert(op.key, op.val)
+    assert slab_counts(mem) == seq.slabs()
+    assert WM.live_multiset(mem) == sorted((0, x[0], x[1]) for x in seq.b[0])
+
+
+@pytest.mark.parametrize("M", [2, 4])
+def test_growth_race_exact(M):
+    for sd in range(N):
+        growth_race_case(M, sd)
+
+
 def test_schedules_reach_the_rare_paths():
-    """The schedules do reach the interleavings that matter: links lost to another wavefront,
-    and a new slab's slot 0 filled by another insert before the linking op's pair lands."""
+    """The schedules do reach the interleavings that matter: a new slab's slot 0 filled by
+    another insert before the linking op's pair lands."""
     tr = []
     for sd in range(3000):
-        unique_mixed_case(4, sd, traces=tr)
+        growth_race_case(4, sd, traces=tr)
     kinds = {t[0] for t in tr}
     assert "link" in kinds and "slot 0 taken before the pair" in kinds

@@ -11,8 +11,8 @@ Each wavefront takes a chunk of ops and works on it in rounds, as the HIP kernel
           A unique-key insert that loses its empty slot walks on with the occupants its swaps
           return; a duplicates-mode insert tries the other empty slots its snapshot showed;
           any other lost swap re-reads the slab next round;
-  grow    ops that found a full tail each take a free pool slab (a step) and link it with a
-          swap on the tail's next index; with unique keys a swap of the pair into slot 0 of
+  grow    the first op (in lane order) that found a full tail takes a free pool slab (a step)
+          and links it with a swap on the tail's next index (the others re-read next round); with unique keys a swap of the pair into slot 0 of
           the new slab is issued together with the link, the two landing in either order; a
           lost link takes the pair back out, frees the slab and follows the winner's slab.
 A scheduler interleaves the steps of all wavefronts at random. The model shares nothing with
@@ -219,7 +219,8 @@ def wavefront(mem, ops, dup, rng, trace, plant=None):
 
         finished = []
         gens = []
-        for op, u in grow:
+        # one op per round and wavefront grows a list; the others re-read their tail next round
+        for op, u in grow[:1]:
             yield
             free = [i for i in range(mem.P) if not mem.allocated[i]]
             if not free:
