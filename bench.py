@@ -1047,24 +1047,24 @@ def main():
     ev_warm = {k: [] for k in names}
     ev_timed = {k: [] for k in names}
 
-    def timed(name, fn, record, ev):
+    def timed(name, fn, record, ev, s):
         if name in record:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
+            e0.record(s)
             fn()
-            e1.record(stream)
+            e1.record(s)
             ev[name].append((e0, e1))
         else:
             fn()
 
-    def step(record, ev):
-        timed("reset", lambda: S.sh_reset(h, stream), record, ev)
-        timed("build", lambda: S.sh_build(h, keys, vals, st_build, stream), record, ev)
-        timed("search_hit", lambda: S.sh_search(h, q_hit, v_out, f_out, stream), record, ev)
-        timed("search_miss", lambda: S.sh_search(h, q_miss, v_out, f_out, stream), record, ev)
+    def step(record, ev, s=stream):
+        timed("reset", lambda: S.sh_reset(h, s), record, ev, s)
+        timed("build", lambda: S.sh_build(h, keys, vals, st_build, s), record, ev, s)
+        timed("search_hit", lambda: S.sh_search(h, q_hit, v_out, f_out, s), record, ev, s)
+        timed("search_miss", lambda: S.sh_search(h, q_miss, v_out, f_out, s), record, ev, s)
         for o, k, v in mix_dev:
-            timed("mixed", lambda: S.sh_mixed(h, o, k, v, mv_out, ms_out, stream), record, ev)
+            timed("mixed", lambda: S.sh_mixed(h, o, k, v, mv_out, ms_out, s), record, ev, s)
 
     def means(ev):
         return {k: (sum(a.elapsed_time(b) for a, b in v) / len(v)) for k, v in ev.items() if v}
@@ -1092,6 +1092,37 @@ def main():
     value = ops_step / ((t1 - t0) / args.steps) / 1e6
     avg_ms[dom] = means(ev_timed)[dom]  # the dominant kernel: timed-region events
     per_step_ms[dom] = avg_ms[dom] * (MIX_BATCHES if dom == "mixed" else 1)
+
+    # The same step captured once into a HIP graph (sh_capture_begin/end on a side stream) and
+    # replayed: one submission per step instead of twenty launches. Its outputs are checked
+    # after the replays.
+    log("graph-replayed steps")
+    gs = torch.cuda.Stream()
+    S.sh_capture_begin(gs)
+    try:
+        step(set(), None, gs)
+    finally:
+        g_step = S.sh_capture_end(gs)
+    try:
+        for _ in range(2):
+            S.sh_graph_launch(g_step, gs)
+        gs.synchronize()
+        ge0 = torch.cuda.Event(enable_timing=True)
+        ge1 = torch.cuda.Event(enable_timing=True)
+        ge0.record(gs)
+        for _ in range(args.steps):
+            S.sh_graph_launch(g_step, gs)
+        ge1.record(gs)
+        gs.synchronize()
+        graph_ms_step = ge0.elapsed_time(ge1) / args.steps
+    finally:
+        S.sh_graph_destroy(g_step)
+    assert bool((st_build == 1).all()) and not bool(f_out.any())
+    graph_steps = {"ms_per_step": round(graph_ms_step, 4),
+                   "Mops": round(ops_step / (graph_ms_step * 1e-3) / 1e6, 2),
+                   "steps": args.steps,
+                   "note": "the timed step's calls captured once with sh_capture_begin/end "
+                           "and replayed as one graph per step"}
 
     # The table as a step leaves it (the next step's reset starts from this), then the
     # structure of the built table (before the mixed batches) for the byte accounting, with
@@ -1257,6 +1288,7 @@ def main():
             "slabs_per_miss": round(v_miss, 4),
         },
         "kernels": kernels,
+        "graph_steps": graph_steps,
         "build_counters": build_counters,
         "roofline": roof,
         "access_patterns": patterns,

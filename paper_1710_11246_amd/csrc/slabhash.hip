@@ -324,15 +324,19 @@ __device__ __forceinline__ void alloc_preload(const View &T, Alloc &s, uint32_t 
 {
     if (T.total_blocks == 0 || s.blk != kEmpty)
         return;
-    s.nact = T.nsuper == 1 ? T.nblk : blocks_in_use(T, load_word_coherent(T.grown));
+    const uint32_t g = T.nsuper == 1 ? 0u : load_word_coherent(T.grown);
+    s.nact = T.nsuper == 1 ? T.nblk : blocks_in_use(T, g);
     s.moves = 0;
-    if (s.nact == 0) {
-        // the table's own pool is empty: start in the first registered super block
+    // start in the newest super block in use (the older ones had filled up when it was
+    // reached); the cyclic moves still cover every block in use
+    const uint32_t first = (g == 0 || g >= T.nsuper) ? 0u : T.dir[g].first;
+    if (s.nact <= first) {
+        // nothing in use yet (the table's own pool is empty): the first registered super block
         if (!alloc_grow(T, s, lane))
             s.full = true;
         return;
     }
-    alloc_goto(T, s, s.start % s.nact, lane);
+    alloc_goto(T, s, first + s.start % (s.nact - first), lane);
 }
 
 __device__ uint32_t wave_alloc(const View &T, Alloc &s, uint32_t lane)
