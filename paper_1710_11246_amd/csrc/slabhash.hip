@@ -530,6 +530,7 @@ struct WaveLds {
     uint64_t msg[64];
     uint32_t key[64];
     uint32_t op[64];
+    uint32_t claimed[64]; // slabs the round's bitmap claims won, in rotated lane order
 };
 
 // The inputs of one chunk, one op per lane (lanes past the chunk's end hold no op).
@@ -834,7 +835,7 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
                 al.lost += (uint32_t)__popcll(ballot((claim_m & claim_old) != 0u));
                 uint32_t served;
                 uint32_t at = rotated_scan((uint32_t)__popc(got_m), lane, al.rot, &served);
-                uint32_t *claimed = reinterpret_cast<uint32_t *>(L.p); // scratch: loads are done
+                uint32_t *claimed = L.claimed;
                 for (uint32_t w = got_m; w; w &= w - 1u)
                     claimed[at++] = al.code + lane * 32 + (uint32_t)__builtin_ctz(w);
                 if (served)
@@ -1671,16 +1672,13 @@ sh_status_t check_launch()
 // unique-key pair tables inserts and deletes at 16 ops per wavefront use 78 VGPRs (24
 // wavefronts fit per CU) and ran fastest at 20 per CU (2^22-pair build 254 us against 330 us
 // at 64 ops and 16 per CU); searches ran fastest at 32 ops, 16 per CU (72 VGPRs). Tables with
-// flags take 64-op chunks, halved for small batches like the others, and always run the full
-// 32-load straight run (104 to 132 VGPRs).
+// flags (duplicates, key-only slabs) take the same shapes.
 struct Shape {
     uint32_t waves_per_cu, max_ops;
 };
 
-Shape default_shape(const sh_table *t, int kind)
+Shape default_shape(const sh_table *, int kind)
 {
-    if (t->v.mode != 0)
-        return {kDefaultWavesPerCU, 64};
     switch (kind) {
     case kSearch:
         return {16, 32};
@@ -1806,9 +1804,7 @@ OpsFn ops_fn_mode(uint32_t C)
                              : C == 16 ? ops_kernel<K, Dup, KO, 8> : ops_kernel<K, Dup, KO, 4>;
 }
 
-// The operation kernel for kind K on table t at C ops per wavefront: unique-key pair tables run
-// a straight run of C / 2 loads per round, tables with flags the full 32 (their chunks may
-// still be shorter).
+// The operation kernel for kind K on table t at C ops per wavefront.
 template <int K>
 OpsFn ops_fn(const sh_table *t, uint32_t C)
 {
@@ -1816,11 +1812,11 @@ OpsFn ops_fn(const sh_table *t, uint32_t C)
     case 0:
         return ops_fn_mode<K, false, false>(C);
     case SH_TABLE_DUPLICATES:
-        return ops_kernel<K, true, false, 32>;
+        return ops_fn_mode<K, true, false>(C);
     case SH_TABLE_KEYS_ONLY:
-        return ops_kernel<K, false, true, 32>;
+        return ops_fn_mode<K, false, true>(C);
     default:
-        return ops_kernel<K, true, true, 32>;
+        return ops_fn_mode<K, true, true>(C);
     }
 }
 
