@@ -525,7 +525,9 @@ def sweep_utilisation(wl0, n_seeds: int = 5, reps: int = 3) -> dict:
     """Bulk build of 2^22 keys, then 2^22 all-hit and 2^22 all-miss searches, at every
     utilisation target's bucket count, for `n_seeds` independent workloads (the first is the
     step's). Per seed: the median of `reps` runs after one untimed run; reported: the median
-    over seeds in M ops/s, the range over seeds, and the achieved utilisation's range."""
+    over seeds in M ops/s, the range over seeds, the achieved utilisation's range, and for the
+    first workload the algorithmic bytes (op_bytes, with that table's own slabs per hit and per
+    miss) over the median time as a fraction of HBM peak."""
     import torch
     from paper_1710_11246_amd import slabhash as S
     from paper_1710_11246_amd import workload as W
@@ -562,6 +564,19 @@ def sweep_utilisation(wl0, n_seeds: int = 5, reps: int = 3) -> dict:
             per[u]["util"].append(8.0 * s_u["live"] / (256.0 * s_u["slabs_total"]))
             for nm in names:
                 per[u][nm].append(N_KEYS / (float(np.median(res[nm])) * 1e-3) / 1e6)
+            if si == 0:
+                _, _, _, counts, viol = tu.dump()
+                assert viol == 0
+                v_hit = chain_visits(counts[:, 0].astype(np.int64) + counts[:, 1]) / N_KEYS
+                v_miss = float(counts[:, 2].mean())
+                kinds = {"build": "insert", "search_hit": "search_hit",
+                         "search_miss": "search_miss"}
+                per[u]["frac_hbm"] = {
+                    nm: round(op_bytes(kinds[nm], N_KEYS, v_hit, v_miss,
+                                       new_slabs=s_u["pool_allocated"] if nm == "build" else 0)
+                              / (float(np.median(res[nm])) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                    for nm in names}
+                per[u]["slabs_per_miss"] = round(v_miss, 4)
             del tu
         del keys, vals, q_hit, q_miss
     out = {"seeds": n_seeds, "reps_per_seed": reps}
@@ -572,7 +587,64 @@ def sweep_utilisation(wl0, n_seeds: int = 5, reps: int = 3) -> dict:
             xs = per[u][nm]
             r[nm] = round(float(np.median(xs)), 1)
             r[nm + "_range"] = [round(min(xs), 1), round(max(xs), 1)]
+        r["frac_hbm"] = per[u]["frac_hbm"]
+        r["slabs_per_miss"] = per[u]["slabs_per_miss"]
         out[str(u)] = r
+    return out
+
+
+def measure_config1(reps: int = 20) -> dict:
+    """The small phased configuration: 2^16 unique keys (value = SplitMix64 finaliser of the
+    key, seed 1) bulk-built into 2^12 buckets, 2^16 searches (half present, half absent), a
+    random 25% of the keys deleted, the searches again. Median of `reps` passes after one
+    untimed pass, each on a reset table; every result is checked against the first pass."""
+    import torch
+    from paper_1710_11246_amd import slabhash as S
+    from paper_1710_11246_amd import workload as W
+    n = 1 << 16
+    wl = W.phased(seed=1, n=n, n_queries=n, hit_fraction=0.5, delete_fraction=0.25,
+                  prime=S.SH_HASH_PRIME)
+    t = S.SlabHash(1 << 12, S.pool_slabs_bound(n), wl.hash_a, wl.hash_b)
+    kd, vd = S.to_dev(wl["keys"]), S.to_dev(wl["vals"])
+    qd, dd = S.to_dev(wl["queries"]), S.to_dev(wl["deletes"])
+    st = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ds = torch.empty(dd.numel(), dtype=torch.uint8, device="cuda")
+    vo = torch.empty(n, dtype=torch.int32, device="cuda")
+    fo = torch.empty(n, dtype=torch.uint8, device="cuda")
+    names = ("build", "search", "delete", "search_after")
+    res = {k: [] for k in names}
+    first = None
+    for rep in range(reps + 1):
+        t.reset()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record()
+        S.sh_build(t.handle, kd, vd, st)
+        e[1].record()
+        S.sh_search(t.handle, qd, vo, fo)
+        e[2].record()
+        f1 = fo.clone()
+        S.sh_delete(t.handle, dd, ds)
+        e[3].record()
+        S.sh_search(t.handle, qd, vo, fo)
+        e[4].record()
+        torch.cuda.synchronize()
+        outs = (st.clone(), f1, ds.clone(), fo.clone(), vo.clone())
+        if first is None:
+            first = outs
+        assert all(bool((a == b).all()) for a, b in zip(outs, first))
+        if rep:
+            for i, k in enumerate(names):
+                res[k].append(e[i].elapsed_time(e[i + 1]))
+    counts = {"build": n, "search": n, "delete": int(dd.numel()), "search_after": n}
+    out = {"workload": "2^16 keys into 2^12 buckets; 2^16 searches (50% present); delete 25%; "
+                       "search again", "reps": reps}
+    for k in names:
+        ms = float(np.median(res[k]))
+        out[k] = {"median_us": round(ms * 1e3, 2), "Mops": round(counts[k] / (ms * 1e-3) / 1e6, 1)}
+    total = sum(float(np.median(res[k])) for k in names)
+    out["pass_us"] = round(total * 1e3, 2)
+    out["pass_Mops"] = round(sum(counts.values()) / (total * 1e-3) / 1e6, 1)
+    del t
     return out
 
 
@@ -967,7 +1039,7 @@ def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
 
 def run_only(sections) -> dict:
     """The named sections alone (no timed step), each as the full run reports it."""
-    runners = {"alloc": measure_alloc, "hbm": measure_hbm_resident,
+    runners = {"alloc": measure_alloc, "hbm": measure_hbm_resident, "config1": measure_config1,
                "duplicates": measure_duplicates,
                "keys_only": measure_keys_only, "batched": run_batched,
                "concurrent": run_concurrent, "served": run_served}
@@ -987,9 +1059,9 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
-                    help="also time build/search at every utilisation target")
+                    help="run the utilisation sweep over --sweep-seeds workloads (default: one)")
     ap.add_argument("--sweep-seeds", type=int, default=5,
-                    help="independent workloads of the utilisation sweep")
+                    help="independent workloads of the utilisation sweep with --sweep")
     ap.add_argument("--sweep-sizes", action="store_true",
                     help="also time build/search for table sizes 2^16 .. 2^26 at utilisation 0.6")
     ap.add_argument("--sweep-batches", action="store_true",
@@ -1002,7 +1074,7 @@ def main():
                     help="skip the incremental-growth and concurrent-batch section")
     ap.add_argument("--only", default="",
                     help="comma-separated sections to run alone, without the timed step (for "
-                         "profiling runs): alloc, flush, duplicates, keys_only, hbm, batched, "
+                         "profiling runs): alloc, config1, duplicates, keys_only, hbm, batched, "
                          "concurrent, served")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device once (a reference "
@@ -1226,9 +1298,12 @@ def main():
                                                                  src.numel() * 4))
         del src, dst
 
-    sweep = None
-    if args.sweep:
-        sweep = sweep_utilisation(wl, args.sweep_seeds)
+    config1 = sweep = None
+    if not args.step_only:
+        log("small phased configuration (2^16 keys, 2^12 buckets)")
+        config1 = measure_config1()
+        log("utilisation sweep")
+        sweep = sweep_utilisation(wl, args.sweep_seeds if args.sweep else 1)
 
     sizes = None
     if args.sweep_sizes:
@@ -1300,6 +1375,8 @@ def main():
         "cpu_baseline": cpu,
         "cpu_partitioned": cpu_part,
     }
+    if config1 is not None:
+        out["config_small_phased"] = config1
     if sweep is not None:
         out["sweep"] = sweep
     if sizes is not None:

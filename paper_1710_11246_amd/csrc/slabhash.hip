@@ -158,39 +158,55 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t k, uint32_t a, uint32_t b
     return r % B;
 }
 
+// Every table access goes through a global-address-space pointer: slab and bitmap addresses
+// are often read back from LDS or from the super-block directory, where the compiler can no
+// longer tell that they point to device memory, and would otherwise emit FLAT instructions.
+// A FLAT access also counts against the LDS counter, so each LDS read between the loads of a
+// straight run would wait for the loads issued before it.
+template <typename X>
+__device__ __forceinline__ __attribute__((address_space(1))) X *gmem(X *p)
+{
+    return (__attribute__((address_space(1))) X *)p;
+}
+
 template <bool Coherent>
 __device__ __forceinline__ uint64_t load_slot(const uint64_t *p)
 {
     if constexpr (Coherent)
-        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __hip_atomic_load(gmem(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
-        return *p;
+        return *gmem(p);
 }
 
 __device__ __forceinline__ uint32_t load_word_coherent(const uint32_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(gmem(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t cas64(uint64_t *p, uint64_t expected, uint64_t desired)
 {
-    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+    __hip_atomic_compare_exchange_strong(gmem(p), &expected, desired, __ATOMIC_RELAXED,
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return expected; // the value found at p (equal to `expected` on success)
 }
 
 __device__ __forceinline__ uint32_t cas32(uint32_t *p, uint32_t expected, uint32_t desired)
 {
-    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+    __hip_atomic_compare_exchange_strong(gmem(p), &expected, desired, __ATOMIC_RELAXED,
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return expected;
+}
+
+__device__ __forceinline__ uint32_t or32(uint32_t *p, uint32_t m)
+{
+    return __hip_atomic_fetch_or(gmem(p), m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void raise_error(const View &T, uint32_t bits, uint32_t lane,
                                             uint32_t who)
 {
     if (lane == who)
-        __hip_atomic_fetch_or(&T.hdr->err, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        or32(&T.hdr->err, bits);
 }
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x)
@@ -222,7 +238,7 @@ __device__ __forceinline__ uint64_t *pool_slab(const View &T, uint32_t idx)
     const uint32_t sb = idx >> kSuperShift;
     if (sb == 0)
         return T.pool + (size_t)idx * 32;
-    return T.dir[sb].pool + (size_t)(idx & kSlabInSuper) * 32;
+    return gmem(T.dir)[sb].pool + (size_t)(idx & kSlabInSuper) * 32;
 }
 
 __device__ __forceinline__ uint64_t *cursor_slab(const View &T, uint32_t loc, uint32_t bkt)
@@ -236,14 +252,14 @@ __device__ __forceinline__ bool pool_in_range(const View &T, uint32_t idx)
     const uint32_t sb = idx >> kSuperShift;
     if (sb == 0)
         return idx < T.pool_slabs;
-    return sb < T.nsuper && (idx & kSlabInSuper) < T.dir[sb].slabs;
+    return sb < T.nsuper && (idx & kSlabInSuper) < gmem(T.dir)[sb].slabs;
 }
 
 // The bitmap word holding pool slab idx's bit (bit idx mod 32).
 __device__ __forceinline__ uint32_t *bitmap_word(const View &T, uint32_t idx)
 {
     const uint32_t sb = idx >> kSuperShift, i = idx & kSlabInSuper;
-    uint32_t *bm = sb ? T.dir[sb].bitmap : T.bitmap;
+    uint32_t *bm = sb ? gmem(T.dir)[sb].bitmap : T.bitmap;
     return bm + (size_t)(i >> 11) * 64 + ((i >> 5) & 63);
 }
 
@@ -258,17 +274,17 @@ __device__ __forceinline__ void block_ref(const View &T, uint32_t g, uint32_t *&
         return;
     }
     uint32_t sb = 1;
-    while (sb + 1 < T.nsuper && T.dir[sb + 1].first <= g)
+    while (sb + 1 < T.nsuper && gmem(T.dir)[sb + 1].first <= g)
         ++sb;
-    const uint32_t lb = g - T.dir[sb].first;
-    row = T.dir[sb].bitmap + (size_t)lb * 64;
+    const uint32_t lb = g - gmem(T.dir)[sb].first;
+    row = gmem(T.dir)[sb].bitmap + (size_t)lb * 64;
     code = (sb << kSuperShift) | (lb * SH_BLOCK_SLABS);
 }
 
 // Blocks of super block 0 and of the `grown` super blocks after it.
 __device__ __forceinline__ uint32_t blocks_in_use(const View &T, uint32_t grown)
 {
-    return 1 + grown >= T.nsuper ? T.total_blocks : T.dir[1 + grown].first;
+    return 1 + grown >= T.nsuper ? T.total_blocks : gmem(T.dir)[1 + grown].first;
 }
 
 struct Alloc {
@@ -329,7 +345,7 @@ __device__ __forceinline__ void alloc_preload(const View &T, Alloc &s, uint32_t 
     s.moves = 0;
     // start in the newest super block in use (the older ones had filled up when it was
     // reached); the cyclic moves still cover every block in use
-    const uint32_t first = (g == 0 || g >= T.nsuper) ? 0u : T.dir[g].first;
+    const uint32_t first = (g == 0 || g >= T.nsuper) ? 0u : gmem(T.dir)[g].first;
     if (s.nact <= first) {
         // nothing in use yet (the table's own pool is empty): the first registered super block
         if (!alloc_grow(T, s, lane))
@@ -360,8 +376,7 @@ __device__ uint32_t wave_alloc(const View &T, Alloc &s, uint32_t lane)
             if (lane == l) {
                 const uint32_t bit = (uint32_t)__builtin_ctz(~s.word);
                 const uint32_t m = 1u << bit;
-                const uint32_t old = __hip_atomic_fetch_or(&s.row[l], m, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t old = or32(&s.row[l], m);
                 s.word = old | m;
                 if (!(old & m))
                     got = s.code + l * 32 + bit;
@@ -444,8 +459,7 @@ __device__ uint32_t wave_alloc_many(const View &T, Alloc &s, uint32_t lane, uint
         }
         uint32_t mine = 0;
         if (m) {
-            const uint32_t old =
-                __hip_atomic_fetch_or(&s.row[lane], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t old = or32(&s.row[lane], m);
             mine = m & ~old;
             s.word = old | m;
         }
@@ -483,7 +497,7 @@ __device__ __forceinline__ uint32_t claim_plan(const Alloc &s, uint32_t lane, ui
 
 __device__ __forceinline__ void slab_free(const View &T, uint32_t idx)
 {
-    __hip_atomic_fetch_and(bitmap_word(T, idx), ~(1u << (idx & 31)), __ATOMIC_RELAXED,
+    __hip_atomic_fetch_and(gmem(bitmap_word(T, idx)), ~(1u << (idx & 31)), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -705,8 +719,7 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
             if (alloc_m) {
                 claim_m = claim_plan(al, lane, 1u);
                 if (claim_m)
-                    claim_old = __hip_atomic_fetch_or(&al.row[lane], claim_m, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
+                    claim_old = or32(&al.row[lane], claim_m);
             }
             bool won = false, lost = false;
             if (KO && code >= kMsgSwapIns) {
@@ -920,13 +933,12 @@ __device__ __forceinline__ void flush_counters(const View &T, const Counters &cn
                                                const Alloc &al, uint32_t wave)
 {
     if (lane_id() == 0) {
-        unsigned long long *cs = T.counters + (size_t)(wave % kCounterSlots) * 8;
-        atomicAdd(cs + 0, (unsigned long long)cnt.rounds);
-        atomicAdd(cs + 1, (unsigned long long)cnt.cas_lost);
-        atomicAdd(cs + 2, (unsigned long long)cnt.allocs);
-        atomicAdd(cs + 3, (unsigned long long)cnt.link_lost);
-        atomicAdd(cs + 4, (unsigned long long)al.total_moves);
-        atomicAdd(cs + 5, (unsigned long long)al.lost);
+        auto cs = gmem(T.counters + (size_t)(wave % kCounterSlots) * 8);
+        const unsigned long long add[6] = {cnt.rounds, cnt.cas_lost, cnt.allocs, cnt.link_lost,
+                                           al.total_moves, al.lost};
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+            __hip_atomic_fetch_add(cs + f, add[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
