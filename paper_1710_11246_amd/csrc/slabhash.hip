@@ -963,8 +963,9 @@ __global__ __launch_bounds__(kBlock) void ops_kernel(View T, const uint8_t *__re
                                                      const uint32_t *__restrict__ vals,
                                                      uint64_t n, uint32_t *__restrict__ vout,
                                                      uint8_t *__restrict__ sout, uint32_t seq,
-                                                     uint32_t C, uint32_t flags)
+                                                     uint32_t flags)
 {
+    constexpr uint32_t C = 2 * NQ; // ops per chunk, two per load of the straight run
     __shared__ WaveLds lds[kWavesPerBlock];
     const uint32_t wl_ = threadIdx.x >> 6;
     const uint32_t wave = blockIdx.x * kWavesPerBlock + wl_;
@@ -1001,8 +1002,9 @@ __global__ __launch_bounds__(kBlock) void multi_kernel(const View *__restrict__ 
                                                        const uint32_t *__restrict__ vals,
                                                        uint32_t *__restrict__ vout,
                                                        uint8_t *__restrict__ sout, uint32_t seq,
-                                                       uint32_t C, uint32_t flags)
+                                                       uint32_t flags)
 {
+    constexpr uint32_t C = 2 * NQ; // ops per chunk, two per load of the straight run
     __shared__ WaveLds lds[kWavesPerBlock];
     // chunk counts in 64 bits (up to 4096 descriptors of up to 2^32 - 1 ops each); pre[] holds
     // nb + 1 entries in the launch's dynamic LDS
@@ -1804,7 +1806,7 @@ sh_status_t launch_init(sh_table *t, void *stream)
 }
 
 using OpsFn = void (*)(View, const uint8_t *, const uint32_t *, const uint32_t *, uint64_t,
-                      uint32_t *, uint8_t *, uint32_t, uint32_t, uint32_t);
+                      uint32_t *, uint8_t *, uint32_t, uint32_t);
 
 // The operation kernel for kind K at C ops per wavefront, in one table mode: a straight run of
 // C / 2 loads per round, one per op pair.
@@ -1865,7 +1867,7 @@ sh_status_t launch_ops(sh_table *t, const uint8_t *ops, const uint32_t *keys,
     const dim3 grid(grid_for(t, n, C, wpc));
     const uint32_t seq = next_seq(&t->seq);
     hipLaunchKernelGGL(fn, grid, dim3(kBlock), 0, S(stream), t->v, ops, keys, vals, n, vout, sout,
-                       seq, C, t->flags);
+                       seq, t->flags);
     return check_launch();
 }
 
@@ -1977,7 +1979,7 @@ uint32_t blocks_for(uint64_t waves)
 
 using MultiFn = void (*)(const View *, uint32_t, const sh_batch_desc_t *, uint32_t, uint64_t,
                         const uint8_t *, const uint32_t *, const uint32_t *, uint32_t *,
-                        uint8_t *, uint32_t, uint32_t, uint32_t);
+                        uint8_t *, uint32_t, uint32_t);
 
 // One batched launch; wpc = 0 takes the default waves per CU (lowered to what fits at once).
 sh_status_t launch_multi_raw(const View *d_dir, uint32_t T, const sh_batch_desc_t *d_desc,
@@ -2006,7 +2008,7 @@ sh_status_t launch_multi_raw(const View *d_dir, uint32_t T, const sh_batch_desc_
         w = chunks;
     hipLaunchKernelGGL(fn, dim3(blocks_for(w)), dim3(kBlock), multi_lds_bytes(nb), stream,
                        d_dir, T, d_desc, nb,
-                       n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, C, flags);
+                       n_ops, d_ops, d_keys, d_vals_in, d_vals_out, d_status, seq, flags);
     return check_launch();
 }
 
