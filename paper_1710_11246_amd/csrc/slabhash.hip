@@ -511,13 +511,16 @@ __device__ __forceinline__ void slab_free(const View &T, uint32_t idx)
 //      (lanes 0..31 read op 2q's slab, lanes 32..63 op 2q+1's), all loads issued up front in one
 //      straight run (a pair with no unfinished op reads slab 0).
 //   2. decide: the ops are taken in lane order, a pair per step. The wavefront votes on each
-//      slab for the op's key (and, for inserts, for empty slots). Exactly one lane of each half
-//      is the op's target: the slot holding the key, else (inserts) the first empty slot, else
-//      slot 31, which holds the next-slab index. The target lane writes the op's outcome to the
-//      op's cell in LDS: found (with the value), a swap to record (insert into the empty slot,
-//      replace the key's value, tombstone the key; with the observed value), move on to the
-//      next slab (with its index), end of list, or a new slab needed.
-//   3. each op reads its cell: searches finish or move; updates record their swap; the swaps
+//      slab for the op's key (and, for inserts, for empty slots). The op's slot is the slot
+//      holding the key, else (inserts) the first empty slot, else slot 31, which holds the
+//      next-slab index. On key-value slabs each op receives its half of the votes in its own
+//      lane and decides there, fetching the one word it needs (the value at its key, or the
+//      next index) from the slab lane that holds it; on key-only slabs the target lane writes
+//      the outcome to the op's cell in LDS. The outcome: found (with the value), a swap to
+//      record (insert into the empty slot, replace the key's value, tombstone the key; with the
+//      observed value), move on to the next slab (with its index), end of list, or a new slab
+//      needed.
+//   3. each op acts on its outcome: searches finish or move; updates record their swap; the swaps
 //      are issued together as one vector atomic. An insert that loses its empty slot learns the
 //      slot's new occupant from the swap: the same key turns it into a replace of that slot,
 //      another key sends it to the following slot at once. Slots fill in order, so this walk
@@ -599,7 +602,7 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
     const bool act = in && !reserved && op <= 2;
     const uint32_t bkt = act ? bucket_of(key, T.a, T.b, T.B) : 0u;
     L.key[lane] = key;
-    if constexpr (K == kMixed)
+    if constexpr (K == kMixed && KO)
         L.op[lane] = op;
 
     uint32_t rv = kEmpty, rs = 0; // this lane's results
@@ -618,82 +621,144 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
             const uint64_t *sp = reinterpret_cast<const uint64_t *>(L.p[2 * q + half]);
             pre[q] = load_slot<kCoherent>(sp + slot);
         }
-        // ---- 2. decide: the target lane of each op writes the op's outcome ----
+        // ---- 2. decide ----
+        uint64_t outcome = 0;
+        if constexpr (!KO) {
+            // Key-value slabs: the wavefront votes on each pair's two slabs (one ballot of
+            // `slot == key`, and for updates one of `slot == empty`) and hands each op its
+            // half of the votes, in the op's own lane. Each op then decides alone. Slot 31
+            // holds the auxiliary half (all ones) and the next index: it never matches a key,
+            // and it votes empty exactly when the slab has no next slab.
+            uint32_t kmv = 0, emv = 0; // this lane's op: key votes, empty votes of its slab
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            if (!((todo >> (2 * q)) & 3ull))
-                continue;
-            const uint64_t w = pre[q];
-            const uint32_t lo = (uint32_t)w;
-            uint32_t hi = (uint32_t)(w >> 32);
-            // keep `hi` a 32-bit register value, so tests on it stay 32-bit compares
-            asm("" : "+v"(hi));
-            const uint32_t kq = L.key[2 * q + half];
-            // a key-value slab holds one pair per lane (key in lo); a key-only slab two keys per
-            // lane, entries 2 slot (lo) and 2 slot + 1 (hi)
-            // votes come straight from the compares (slot 31 holds the next index, not a pair)
-            const uint64_t mlo_m = ballot(lo == kq) & kSlotLanes;
-            const uint64_t mhi_m = KO ? (ballot(hi == kq) & kSlotLanes) : 0ull;
-            const bool mlo = inverse_ballot(mlo_m);
-            const bool mhi = KO && inverse_ballot(mhi_m);
-            const bool match = mlo || mhi;
-            const uint32_t kh = (uint32_t)((mlo_m | mhi_m) >> hshift); // my half's key votes
-            // the op's slot is the first match of the slab (with unique keys the only one)
-            const bool is_key = Dup ? (match && (kh & below) == 0u) : match;
-            const uint32_t kslot = KO ? (mlo ? 2 * slot : 2 * slot + 1) : slot;
-            bool ins = (K == kInsert);
-            uint32_t code_key = (K == kSearch) ? kMsgFound
-                                               : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
-            if constexpr (K == kMixed) {
-                const uint32_t oq = L.op[2 * q + half];
-                ins = oq == kInsert;
-                code_key = (oq == kSearch) ? kMsgFound
-                                           : ((oq == kDelete) ? kMsgSwapDel : kMsgSwapRep);
+            for (int q = 0; q < NQ; ++q) {
+                if (!((todo >> (2 * q)) & 3ull))
+                    continue;
+                const uint64_t w = pre[q];
+                const uint32_t kq = L.key[2 * q + half];
+                const uint64_t km = ballot((uint32_t)w == kq);
+                kmv = wl(kmv, 2 * q, (uint32_t)km);
+                kmv = wl(kmv, 2 * q + 1, (uint32_t)(km >> 32));
+                if constexpr (kHasIns) {
+                    const uint64_t em = ballot(w == kEmptyPair);
+                    emv = wl(emv, 2 * q, (uint32_t)em);
+                    emv = wl(emv, 2 * q + 1, (uint32_t)(em >> 32));
+                }
             }
-            bool target;
-            uint32_t code, tslot = slot;
-            uint32_t empties = 0;
-            if constexpr (kHasIns) {
-                const uint64_t elo_m = (KO ? ballot(lo == kEmpty) : ballot(w == kEmptyPair)) &
-                                       kSlotLanes;
-                const uint64_t ehi_m = KO ? (ballot(hi == kEmpty) & kSlotLanes) : 0ull;
-                const bool elo = inverse_ballot(elo_m);
-                const bool ehi = KO && inverse_ballot(ehi_m);
-                const bool is_empty = elo || ehi;
-                const uint32_t eh = (uint32_t)((elo_m | ehi_m) >> hshift);
-                empties = eh;
-                const bool first_empty = ins && is_empty && (eh & below) == 0u;
-                const bool tail = is31 && (!ins || eh == 0u);
-                // with duplicates an insert takes the first empty slot whatever keys it meets
-                const bool hit = Dup ? (is_key && !ins) : is_key;
-                const uint32_t khe = (Dup && ins) ? 0u : kh;
-                target = hit || (khe == 0u && (first_empty || tail));
-                code = hit ? code_key
-                           : (first_empty ? kMsgSwapIns
-                                          : (hi != kEmpty ? kMsgMove
-                                                          : (ins ? kMsgGrow : kMsgEnd)));
-                if (hit)
-                    tslot = kslot;
-                else if (first_empty)
-                    tslot = KO ? (elo ? 2 * slot : 2 * slot + 1) : slot;
+            const bool ins = (K == kInsert) || (K == kMixed && op == (uint32_t)kInsert);
+            // the op's slot is its key's first slot (with unique keys the only one); 31: absent
+            const uint32_t kslot = (uint32_t)__builtin_ctz(kmv | 0x80000000u);
+            // the first empty slot; 31: none, and no next slab; 32: none, and a next slab
+            const uint32_t eslot = emv ? (uint32_t)__builtin_ctz(emv) : 32u;
+            // with duplicates an insert takes the first empty slot whatever keys it meets
+            const bool by_key = !(Dup && ins) && kslot < 31u;
+            // the word of the slab the op needs: its key's value, else the next index
+            const uint32_t src = ((lane & 1u) * 32u + (by_key ? kslot : 31u)) * 4u;
+            // (unconditional, so that the fetches are issued back to back; a pair with no
+            // unfinished op read slab 0)
+            uint32_t hv = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const uint32_t h = (uint32_t)__builtin_amdgcn_ds_bpermute(
+                    (int)src, (int)(uint32_t)(pre[q] >> 32));
+                if (inverse_ballot(3ull << (2 * q)))
+                    hv = h;
+            }
+            uint32_t code, tslot = kslot, payload = hv;
+            if (by_key) {
+                code = (K == kSearch) ? kMsgFound : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
+                if constexpr (K == kMixed)
+                    code = (op == (uint32_t)kSearch)
+                               ? kMsgFound
+                               : ((op == (uint32_t)kDelete) ? kMsgSwapDel : kMsgSwapRep);
+            } else if (ins && eslot < 31u) {
+                code = kMsgSwapIns;
+                tslot = eslot;
+                // with duplicates empty slots need not be a suffix: the op carries them all
+                if constexpr (Dup)
+                    payload = emv & (uint32_t)kSlotMask;
             } else {
-                target = is_key || (kh == 0u && is31);
-                code = is_key ? code_key : (hi != kEmpty ? kMsgMove : kMsgEnd);
-                if (is_key)
-                    tslot = kslot;
+                code = hv != kEmpty ? kMsgMove : (ins ? kMsgGrow : kMsgEnd);
             }
-            // the payload: the value found (in a key-only slab, the key itself), the next index,
-            // or for an insert into an empty slot with duplicates, the lanes of the slab that
-            // showed an empty slot (empty slots need not be a suffix there)
-            const uint32_t payload =
-                (Dup && code == kMsgSwapIns) ? empties : ((KO && is_key) ? kq : hi);
-            if (target)
-                L.msg[2 * q + half] = ((uint64_t)((code << 8) | tslot) << 32) | payload;
+            outcome = ((uint64_t)((code << 8) | tslot) << 32) | payload;
+        } else {
+            // Key-only slabs (two entries per lane, entries 2 slot in lo and 2 slot + 1 in hi):
+            // the target lane of each op writes the op's outcome to the op's LDS cell.
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (!((todo >> (2 * q)) & 3ull))
+                    continue;
+                const uint64_t w = pre[q];
+                const uint32_t lo = (uint32_t)w;
+                uint32_t hi = (uint32_t)(w >> 32);
+                // keep `hi` a 32-bit register value, so tests on it stay 32-bit compares
+                asm("" : "+v"(hi));
+                const uint32_t kq = L.key[2 * q + half];
+                // votes come straight from the compares (slot 31 holds the next index)
+                const uint64_t mlo_m = ballot(lo == kq) & kSlotLanes;
+                const uint64_t mhi_m = ballot(hi == kq) & kSlotLanes;
+                const bool mlo = inverse_ballot(mlo_m);
+                const bool mhi = inverse_ballot(mhi_m);
+                const bool match = mlo || mhi;
+                const uint32_t kh = (uint32_t)((mlo_m | mhi_m) >> hshift); // my half's key votes
+                // the op's entry is the first match of the slab (with unique keys the only one)
+                const bool is_key = Dup ? (match && (kh & below) == 0u) : match;
+                const uint32_t kslot = mlo ? 2 * slot : 2 * slot + 1;
+                bool ins = (K == kInsert);
+                uint32_t code_key = (K == kSearch) ? kMsgFound
+                                                   : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
+                if constexpr (K == kMixed) {
+                    const uint32_t oq = L.op[2 * q + half];
+                    ins = oq == kInsert;
+                    code_key = (oq == kSearch) ? kMsgFound
+                                               : ((oq == kDelete) ? kMsgSwapDel : kMsgSwapRep);
+                }
+                bool target;
+                uint32_t code, tslot = slot;
+                uint32_t empties = 0;
+                if constexpr (kHasIns) {
+                    const uint64_t elo_m = ballot(lo == kEmpty) & kSlotLanes;
+                    const uint64_t ehi_m = ballot(hi == kEmpty) & kSlotLanes;
+                    const bool elo = inverse_ballot(elo_m);
+                    const bool ehi = inverse_ballot(ehi_m);
+                    const bool is_empty = elo || ehi;
+                    const uint32_t eh = (uint32_t)((elo_m | ehi_m) >> hshift);
+                    empties = eh;
+                    const bool first_empty = ins && is_empty && (eh & below) == 0u;
+                    const bool tail = is31 && (!ins || eh == 0u);
+                    // with duplicates an insert takes the first empty entry whatever keys it
+                    // meets
+                    const bool hit = Dup ? (is_key && !ins) : is_key;
+                    const uint32_t khe = (Dup && ins) ? 0u : kh;
+                    target = hit || (khe == 0u && (first_empty || tail));
+                    code = hit ? code_key
+                               : (first_empty ? kMsgSwapIns
+                                              : (hi != kEmpty ? kMsgMove
+                                                              : (ins ? kMsgGrow : kMsgEnd)));
+                    if (hit)
+                        tslot = kslot;
+                    else if (first_empty)
+                        tslot = elo ? 2 * slot : 2 * slot + 1;
+                } else {
+                    target = is_key || (kh == 0u && is31);
+                    code = is_key ? code_key : (hi != kEmpty ? kMsgMove : kMsgEnd);
+                    if (is_key)
+                        tslot = kslot;
+                }
+                // the payload: the key itself when found (a search reports it as the value),
+                // the next index, or for an insert into an empty entry with duplicates, the
+                // lanes of the slab that showed an empty entry (they need not be a suffix)
+                const uint32_t payload =
+                    (Dup && code == kMsgSwapIns) ? empties : (is_key ? kq : hi);
+                if (target)
+                    L.msg[2 * q + half] = ((uint64_t)((code << 8) | tslot) << 32) | payload;
+            }
+            __builtin_amdgcn_wave_barrier();
+            outcome = L.msg[lane];
         }
-        __builtin_amdgcn_wave_barrier();
         // ---- 3. act on the outcome ----
         const bool mine = (todo >> lane) & 1;
-        const uint64_t msg = mine ? L.msg[lane] : 0ull;
+        const uint64_t msg = mine ? outcome : 0ull;
         const uint32_t payload = (uint32_t)msg;
         const uint32_t code = mine ? (uint32_t)(msg >> 40) : 0u;
         const uint32_t tslot = (uint32_t)(msg >> 32) & 255u;
