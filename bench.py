@@ -41,18 +41,18 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
 # Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
 # a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
-TRAFFIC_SRC_SHA = "06e3b15626dc944b"
+TRAFFIC_SRC_SHA = "d4dd35a5c1c99956"
 # Per launch, from rocprofv3 TCC_HIT_sum/TCC_MISS_sum and TCC_ATOMIC_sum/TCC_EA0_ATOMIC_sum runs
 # of the same source (profiles/slabhash_step_2p22_l2.md): (L2 hit rate, atomics, atomics that
 # reached memory).
-L2_STATS = {"build": (0.3649, 4801347, 4801347), "search_hit": (0.094, 0, 0),
-            "search_miss": (0.094, 0, 0), "mixed": (0.3201, 26742, 26742),
-            "reset": (0.5022, 0, 0)}
+L2_STATS = {"build": (0.3683, 4695311, 4695311), "search_hit": (0.0927, 0, 0),
+            "search_miss": (0.0927, 0, 0), "mixed": (0.314, 26727, 26727),
+            "reset": (0.5023, 0, 0)}
 # The same for the 2^26-key table of measure_hbm_resident (profiles/slabhash_hbm_2p26_traffic.md).
-HBM_TRAFFIC_BYTES = {"build": 22283906572, "search_hit": 17763795118,
-                     "search_miss": 17763795118}
-TRAFFIC_BYTES = {"build": 1355276792, "search_hit": 1039071403, "search_miss": 1039071403,
-                 "mixed": 19537051, "reset": 56247443}
+HBM_TRAFFIC_BYTES = {"build": 22298798297, "search_hit": 17762453062,
+                     "search_miss": 17762453062}
+TRAFFIC_BYTES = {"build": 1349689800, "search_hit": 1039463238, "search_miss": 1039463238,
+                 "mixed": 19522561, "reset": 56247411}
 
 
 def source_sha() -> str:
