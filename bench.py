@@ -41,18 +41,18 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
 # Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
 # a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
-TRAFFIC_SRC_SHA = "d4dd35a5c1c99956"
+TRAFFIC_SRC_SHA = "e072f92f1e4dcb03"
 # Per launch, from rocprofv3 TCC_HIT_sum/TCC_MISS_sum and TCC_ATOMIC_sum/TCC_EA0_ATOMIC_sum runs
 # of the same source (profiles/slabhash_step_2p22_l2.md): (L2 hit rate, atomics, atomics that
 # reached memory).
-L2_STATS = {"build": (0.3683, 4695311, 4695311), "search_hit": (0.0927, 0, 0),
-            "search_miss": (0.0927, 0, 0), "mixed": (0.314, 26727, 26727),
-            "reset": (0.5023, 0, 0)}
+L2_STATS = {"build": (0.3683, 4694300, 4694300), "search_hit": (0.1276, 0, 0),
+            "search_miss": (0.1276, 0, 0), "mixed": (0.3121, 26725, 26725),
+            "reset": (0.5022, 0, 0)}
 # The same for the 2^26-key table of measure_hbm_resident (profiles/slabhash_hbm_2p26_traffic.md).
-HBM_TRAFFIC_BYTES = {"build": 22298798297, "search_hit": 17762453062,
-                     "search_miss": 17762453062}
-TRAFFIC_BYTES = {"build": 1349689800, "search_hit": 1039463238, "search_miss": 1039463238,
-                 "mixed": 19522561, "reset": 56247411}
+HBM_TRAFFIC_BYTES = {"build": 22297607437, "search_hit": 17761968478,
+                     "search_miss": 17761968478}
+TRAFFIC_BYTES = {"build": 1349636007, "search_hit": 1039320542, "search_miss": 1039320542,
+                 "mixed": 19518108, "reset": 56247454}
 
 
 def source_sha() -> str:
@@ -727,7 +727,9 @@ def measure_hbm_resident(log2n: int = 26, util: float = 0.6, reps: int = 3,
     slabs), then 2^26 all-hit searches (a permutation of the keys) and 2^26 all-miss searches.
     Median of `reps` runs after one untimed run, each build on a reset table, HIP events around
     each call. Every status, found flag and hit value is checked on the device. Algorithmic
-    bytes follow op_bytes with the built table's own slabs per hit and per miss."""
+    bytes follow op_bytes with the built table's own slabs per hit and per miss. Afterwards the
+    access patterns of measure_patterns are timed over a buffer of the table's size, and each
+    kernel is reported against its own pattern's ceiling."""
     import torch
     from paper_1710_11246_amd import autotune as A
     from paper_1710_11246_amd import slabhash as S
@@ -791,8 +793,17 @@ def measure_hbm_resident(log2n: int = 26, util: float = 0.6, reps: int = 3,
                   "bytes_per_launch": int(bytes_l[k]), "algorithmic_GBps": round(gbs, 1),
                   "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
                   "traffic_bytes": HBM_TRAFFIC_BYTES.get(k) if traffic_ok else None}
+    table_bytes = int(t.storage.numel())
     del t, kd, vd, qh, qm, want, st, vo, fo
     torch.cuda.empty_cache()
+    # the same access patterns' ceilings over a buffer of the table's size (random 256-byte
+    # slab reads and swaps from HBM, which the MALL cannot hold)
+    pats = measure_patterns(table_bytes, n, reps=3)
+    out["access_patterns"] = pats
+    for k, pat in (("build", "load_cas"), ("search_hit", "slab_load"),
+                   ("search_miss", "slab_load")):
+        out[k]["pattern_ceiling_ms"] = round(pats[pat + "_us"] / 1e3, 4)
+        out[k]["frac_of_pattern_ceiling"] = round(pats[pat + "_us"] / 1e3 / out[k]["avg_ms"], 4)
     return out
 
 

@@ -24,8 +24,10 @@
  *     call: the affected op gets status 0 (found 0, value 0xFFFFFFFF for a search) and a bit is
  *     set in the table's sticky error word, read by sh_stats.
  *   - sh_search, sh_insert, sh_delete and sh_mixed may run concurrently on one table from
- *     different streams; sh_search reads through caches and is exact for updates ordered
- *     before it, sh_mixed reads coherently and is linearizable against concurrent updates.
+ *     different streams. Every slab read is device-coherent, so each operation is
+ *     linearizable: it takes effect at one instant between its call's start and end on the
+ *     device, and an operation of a call that starts after another call has finished sees all
+ *     of that call's effects.
  *     sh_create, sh_reset, sh_stats and sh_dump must not overlap any other call on
  *     the same table.
  *   - Per-op status: search 1 found / 0 not found; insert 1 new key / 2 replaced the value of
@@ -251,7 +253,8 @@ sh_status_t sh_mixed(sh_table_t *t, const uint8_t *d_ops, const uint32_t *d_keys
    d_vals_out[d_offsets[i] + 1], ..., but never past d_offsets[i + 1] (d_vals_cap for the last
    query): a caller sizes the output from the counts of a first call without them (their
    exclusive prefix sum gives the offsets), and a table changed in between cannot make a query
-   write outside its range. Reads through caches, like sh_search. */
+   write outside its range. With concurrent updates of the same key, an element updated while
+   the list is walked may be reported or not. */
 sh_status_t sh_search_all(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint32_t *d_counts,
                           const uint64_t *d_offsets, uint32_t *d_vals_out, uint64_t d_vals_cap,
                           void *stream);

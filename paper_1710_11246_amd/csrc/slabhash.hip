@@ -169,13 +169,11 @@ __device__ __forceinline__ __attribute__((address_space(1))) X *gmem(X *p)
     return (__attribute__((address_space(1))) X *)p;
 }
 
-template <bool Coherent>
+// One 8-byte slab word, read device-coherently (an agent-scope relaxed atomic load): every
+// kernel sees the swaps of kernels running at the same time on other streams and of other XCDs.
 __device__ __forceinline__ uint64_t load_slot(const uint64_t *p)
 {
-    if constexpr (Coherent)
-        return __hip_atomic_load(gmem(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        return *gmem(p);
+    return __hip_atomic_load(gmem(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint32_t load_word_coherent(const uint32_t *p)
@@ -574,6 +572,75 @@ __device__ __forceinline__ ChunkIn load_chunk(const uint8_t *__restrict__ ops,
     return c;
 }
 
+// The decide step on key-value slabs. The wavefront votes on each pair's two slabs (one ballot
+// of `slot == key`, and for updates one of `slot == empty`) and hands each op its half of the
+// votes, in the op's own lane. Each op then decides alone. Slot 31 holds the auxiliary half (all
+// ones) and the next index: it never matches a key, and it votes empty exactly when the slab has
+// no next slab. pre[q] holds this lane's word of the slab of op 2q (lanes 0..31) or op 2q + 1
+// (lanes 32..63); bits of `todo` name the ops still running (pairs with neither are skipped);
+// L.key holds each op's key and `op` this lane's op kind. Returns this lane's outcome: (code << 8
+// | slot) in the high word, the payload in the low word.
+template <int K, bool Dup, int NQ>
+__device__ __forceinline__ uint64_t decide_kv(const uint64_t (&pre)[NQ], uint64_t todo,
+                                              const WaveLds &L, uint32_t op)
+{
+    constexpr bool kHasIns = (K == kInsert || K == kMixed);
+    const uint32_t lane = lane_id();
+    const uint32_t half = lane >> 5;
+    uint32_t kmv = 0, emv = 0; // this lane's op: key votes, empty votes of its slab
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (!((todo >> (2 * q)) & 3ull))
+            continue;
+        const uint64_t w = pre[q];
+        const uint32_t kq = L.key[2 * q + half];
+        const uint64_t km = ballot((uint32_t)w == kq);
+        kmv = wl(kmv, 2 * q, (uint32_t)km);
+        kmv = wl(kmv, 2 * q + 1, (uint32_t)(km >> 32));
+        if constexpr (kHasIns) {
+            const uint64_t em = ballot(w == kEmptyPair);
+            emv = wl(emv, 2 * q, (uint32_t)em);
+            emv = wl(emv, 2 * q + 1, (uint32_t)(em >> 32));
+        }
+    }
+    const bool ins = (K == kInsert) || (K == kMixed && op == (uint32_t)kInsert);
+    // the op's slot is its key's first slot (with unique keys the only one); 31: absent
+    const uint32_t kslot = (uint32_t)__builtin_ctz(kmv | 0x80000000u);
+    // the first empty slot; 31: none, and no next slab; 32: none, and a next slab
+    const uint32_t eslot = emv ? (uint32_t)__builtin_ctz(emv) : 32u;
+    // with duplicates an insert takes the first empty slot whatever keys it meets
+    const bool by_key = !(Dup && ins) && kslot < 31u;
+    // the word of the slab the op needs: its key's value, else the next index
+    const uint32_t src = ((lane & 1u) * 32u + (by_key ? kslot : 31u)) * 4u;
+    // (unconditional, so that the fetches are issued back to back; every pair's load read a
+    // valid slab)
+    uint32_t hv = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const uint32_t h = (uint32_t)__builtin_amdgcn_ds_bpermute(
+            (int)src, (int)(uint32_t)(pre[q] >> 32));
+        if (inverse_ballot(3ull << (2 * q)))
+            hv = h;
+    }
+    uint32_t code, tslot = kslot, payload = hv;
+    if (by_key) {
+        code = (K == kSearch) ? kMsgFound : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
+        if constexpr (K == kMixed)
+            code = (op == (uint32_t)kSearch)
+                       ? kMsgFound
+                       : ((op == (uint32_t)kDelete) ? kMsgSwapDel : kMsgSwapRep);
+    } else if (ins && eslot < 31u) {
+        code = kMsgSwapIns;
+        tslot = eslot;
+        // with duplicates empty slots need not be a suffix: the op carries them all
+        if constexpr (Dup)
+            payload = emv & (uint32_t)kSlotMask;
+    } else {
+        code = hv != kEmpty ? kMsgMove : (ins ? kMsgGrow : kMsgEnd);
+    }
+    return ((uint64_t)((code << 8) | tslot) << 32) | payload;
+}
+
 // One chunk of up to 2 NQ ops (lane l < count holds op base + l, with inputs `c`) on table T,
 // processed in rounds until every op has finished (see the description above). NQ is the
 // number of op pairs, and so the length of each round's straight run of loads.
@@ -582,7 +649,6 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
                           uint32_t *__restrict__ vout, uint8_t *__restrict__ sout, uint64_t base,
                           uint32_t count, uint32_t flags)
 {
-    constexpr bool kCoherent = (K != kSearch);
     constexpr bool kHasIns = (K == kInsert || K == kMixed);
     // unique-key pair inserts write their pair into a new tail slab before linking it
     constexpr bool kPrefill = !Dup && !KO;
@@ -619,68 +685,12 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const uint64_t *sp = reinterpret_cast<const uint64_t *>(L.p[2 * q + half]);
-            pre[q] = load_slot<kCoherent>(sp + slot);
+            pre[q] = load_slot(sp + slot);
         }
         // ---- 2. decide ----
         uint64_t outcome = 0;
         if constexpr (!KO) {
-            // Key-value slabs: the wavefront votes on each pair's two slabs (one ballot of
-            // `slot == key`, and for updates one of `slot == empty`) and hands each op its
-            // half of the votes, in the op's own lane. Each op then decides alone. Slot 31
-            // holds the auxiliary half (all ones) and the next index: it never matches a key,
-            // and it votes empty exactly when the slab has no next slab.
-            uint32_t kmv = 0, emv = 0; // this lane's op: key votes, empty votes of its slab
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (!((todo >> (2 * q)) & 3ull))
-                    continue;
-                const uint64_t w = pre[q];
-                const uint32_t kq = L.key[2 * q + half];
-                const uint64_t km = ballot((uint32_t)w == kq);
-                kmv = wl(kmv, 2 * q, (uint32_t)km);
-                kmv = wl(kmv, 2 * q + 1, (uint32_t)(km >> 32));
-                if constexpr (kHasIns) {
-                    const uint64_t em = ballot(w == kEmptyPair);
-                    emv = wl(emv, 2 * q, (uint32_t)em);
-                    emv = wl(emv, 2 * q + 1, (uint32_t)(em >> 32));
-                }
-            }
-            const bool ins = (K == kInsert) || (K == kMixed && op == (uint32_t)kInsert);
-            // the op's slot is its key's first slot (with unique keys the only one); 31: absent
-            const uint32_t kslot = (uint32_t)__builtin_ctz(kmv | 0x80000000u);
-            // the first empty slot; 31: none, and no next slab; 32: none, and a next slab
-            const uint32_t eslot = emv ? (uint32_t)__builtin_ctz(emv) : 32u;
-            // with duplicates an insert takes the first empty slot whatever keys it meets
-            const bool by_key = !(Dup && ins) && kslot < 31u;
-            // the word of the slab the op needs: its key's value, else the next index
-            const uint32_t src = ((lane & 1u) * 32u + (by_key ? kslot : 31u)) * 4u;
-            // (unconditional, so that the fetches are issued back to back; a pair with no
-            // unfinished op read slab 0)
-            uint32_t hv = 0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const uint32_t h = (uint32_t)__builtin_amdgcn_ds_bpermute(
-                    (int)src, (int)(uint32_t)(pre[q] >> 32));
-                if (inverse_ballot(3ull << (2 * q)))
-                    hv = h;
-            }
-            uint32_t code, tslot = kslot, payload = hv;
-            if (by_key) {
-                code = (K == kSearch) ? kMsgFound : ((K == kDelete) ? kMsgSwapDel : kMsgSwapRep);
-                if constexpr (K == kMixed)
-                    code = (op == (uint32_t)kSearch)
-                               ? kMsgFound
-                               : ((op == (uint32_t)kDelete) ? kMsgSwapDel : kMsgSwapRep);
-            } else if (ins && eslot < 31u) {
-                code = kMsgSwapIns;
-                tslot = eslot;
-                // with duplicates empty slots need not be a suffix: the op carries them all
-                if constexpr (Dup)
-                    payload = emv & (uint32_t)kSlotMask;
-            } else {
-                code = hv != kEmpty ? kMsgMove : (ins ? kMsgGrow : kMsgEnd);
-            }
-            outcome = ((uint64_t)((code << 8) | tslot) << 32) | payload;
+            outcome = decide_kv<K, Dup, NQ>(pre, todo, L, op);
         } else {
             // Key-only slabs (two entries per lane, entries 2 slot in lo and 2 slot + 1 in hi):
             // the target lane of each op writes the op's outcome to the op's LDS cell.
@@ -1451,7 +1461,7 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
         uint64_t pre[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            pre[q] = load_slot<Del>(T.base + (size_t)uu[2 * q + half] * 32 + slot);
+            pre[q] = load_slot(T.base + (size_t)uu[2 * q + half] * 32 + slot);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             if (2 * (uint32_t)q >= count)
@@ -1519,7 +1529,7 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
                     break;
                 if (go) {
                     up = pool_slab(T, nx);
-                    w = load_slot<Del>(up + slot);
+                    w = load_slot(up + slot);
                 }
             }
             if (slot == 0 && op < count && counts)
