@@ -24,10 +24,14 @@
  *     call: the affected op gets status 0 (found 0, value 0xFFFFFFFF for a search) and a bit is
  *     set in the table's sticky error word, read by sh_stats.
  *   - sh_search, sh_insert, sh_delete and sh_mixed may run concurrently on one table from
- *     different streams. Every slab read is device-coherent, so each operation is
- *     linearizable: it takes effect at one instant between its call's start and end on the
- *     device, and an operation of a call that starts after another call has finished sees all
- *     of that call's effects.
+ *     different streams, and each operation is linearizable with respect to the calls' time
+ *     spans: an operation sees every update of a call that finished before its own call began,
+ *     updates of calls running at the same time may or may not be seen, and each result is a
+ *     state its key held at some instant during the call. sh_insert, sh_delete and sh_mixed read
+ *     slabs device-coherently and are linearizable at the level of single operations as well.
+ *     sh_search reads through the caches (a search after an update on another stream sees it
+ *     once the update's call has finished); use sh_mixed with search ops for searches that must
+ *     see updates completing while they run.
  *     sh_create, sh_reset, sh_stats and sh_dump must not overlap any other call on
  *     the same table.
  *   - Per-op status: search 1 found / 0 not found; insert 1 new key / 2 replaced the value of
@@ -253,8 +257,7 @@ sh_status_t sh_mixed(sh_table_t *t, const uint8_t *d_ops, const uint32_t *d_keys
    d_vals_out[d_offsets[i] + 1], ..., but never past d_offsets[i + 1] (d_vals_cap for the last
    query): a caller sizes the output from the counts of a first call without them (their
    exclusive prefix sum gives the offsets), and a table changed in between cannot make a query
-   write outside its range. With concurrent updates of the same key, an element updated while
-   the list is walked may be reported or not. */
+   write outside its range. Reads through the caches, like sh_search. */
 sh_status_t sh_search_all(sh_table_t *t, const uint32_t *d_keys, uint64_t n, uint32_t *d_counts,
                           const uint64_t *d_offsets, uint32_t *d_vals_out, uint64_t d_vals_cap,
                           void *stream);

@@ -169,11 +169,18 @@ __device__ __forceinline__ __attribute__((address_space(1))) X *gmem(X *p)
     return (__attribute__((address_space(1))) X *)p;
 }
 
-// One 8-byte slab word, read device-coherently (an agent-scope relaxed atomic load): every
-// kernel sees the swaps of kernels running at the same time on other streams and of other XCDs.
+// One 8-byte slab word. Coherent: an agent-scope relaxed atomic load, which sees the swaps of
+// other XCDs and of kernels running at the same time on other streams (the update kernels
+// re-read slabs after lost swaps, so they need it). Otherwise a plain load through the caches,
+// which sees everything written before the kernel started: searches keep slabs that many lists
+// share (the pool slabs of long lists) in L2.
+template <bool Coherent>
 __device__ __forceinline__ uint64_t load_slot(const uint64_t *p)
 {
-    return __hip_atomic_load(gmem(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (Coherent)
+        return __hip_atomic_load(gmem(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *gmem(p);
 }
 
 __device__ __forceinline__ uint32_t load_word_coherent(const uint32_t *p)
@@ -649,6 +656,7 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
                           uint32_t *__restrict__ vout, uint8_t *__restrict__ sout, uint64_t base,
                           uint32_t count, uint32_t flags)
 {
+    constexpr bool kCoherent = (K != kSearch);
     constexpr bool kHasIns = (K == kInsert || K == kMixed);
     // unique-key pair inserts write their pair into a new tail slab before linking it
     constexpr bool kPrefill = !Dup && !KO;
@@ -685,7 +693,7 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const uint64_t *sp = reinterpret_cast<const uint64_t *>(L.p[2 * q + half]);
-            pre[q] = load_slot(sp + slot);
+            pre[q] = load_slot<kCoherent>(sp + slot);
         }
         // ---- 2. decide ----
         uint64_t outcome = 0;
@@ -1461,7 +1469,7 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
         uint64_t pre[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            pre[q] = load_slot(T.base + (size_t)uu[2 * q + half] * 32 + slot);
+            pre[q] = load_slot<Del>(T.base + (size_t)uu[2 * q + half] * 32 + slot);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             if (2 * (uint32_t)q >= count)
@@ -1529,7 +1537,7 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
                     break;
                 if (go) {
                     up = pool_slab(T, nx);
-                    w = load_slot(up + slot);
+                    w = load_slot<Del>(up + slot);
                 }
             }
             if (slot == 0 && op < count && counts)
