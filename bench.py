@@ -670,7 +670,7 @@ def measure_config1(reps: int = 20) -> dict:
     return out
 
 
-def sweep_sizes(log2_sizes=(16, 18, 20, 22, 24, 26), util: float = 0.6, reps: int = 5) -> dict:
+def sweep_sizes(log2_sizes=(16, 18, 20, 22, 24), util: float = 0.6, reps: int = 5) -> dict:
     """Bulk build, all-hit search and all-miss search against table size ("Bulk benchmarks"): n
     distinct uniform keys for each n = 2^k, buckets from the Binomial model for the target
     utilisation, median of `reps` runs (each build on a reset table)."""
@@ -1095,10 +1095,11 @@ def main():
                     help="run the utilisation sweep over --sweep-seeds workloads (default: one)")
     ap.add_argument("--sweep-seeds", type=int, default=5,
                     help="independent workloads of the utilisation sweep with --sweep")
-    ap.add_argument("--sweep-sizes", action="store_true",
-                    help="also time build/search for table sizes 2^16 .. 2^26 at utilisation 0.6")
-    ap.add_argument("--sweep-batches", action="store_true",
-                    help="also time incremental insertion to 2^24 keys in batches of 2^15..2^17")
+    ap.add_argument("--no-sweep-sizes", action="store_true",
+                    help="skip build/search against table size, 2^16 .. 2^24 at utilisation 0.6 "
+                         "(2^26 is the HBM-resident section)")
+    ap.add_argument("--no-sweep-batches", action="store_true",
+                    help="skip incremental insertion to 2^24 keys in batches of 2^15 .. 2^17")
     ap.add_argument("--step-only", action="store_true",
                     help="only the timed step and its per-kernel figures (no other section)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form section")
@@ -1339,11 +1340,11 @@ def main():
         sweep = sweep_utilisation(wl, args.sweep_seeds if args.sweep else 1)
 
     sizes = None
-    if args.sweep_sizes:
+    if not args.step_only and not args.no_sweep_sizes:
         log("size sweep")
         sizes = sweep_sizes()
     batch_sweep = None
-    if args.sweep_batches:
+    if not args.step_only and not args.no_sweep_batches:
         log("batch-size sweep")
         batch_sweep = sweep_batches()
 
