@@ -673,7 +673,8 @@ def measure_config1(reps: int = 20) -> dict:
 def sweep_sizes(log2_sizes=(16, 18, 20, 22, 24), util: float = 0.6, reps: int = 5) -> dict:
     """Bulk build, all-hit search and all-miss search against table size ("Bulk benchmarks"): n
     distinct uniform keys for each n = 2^k, buckets from the Binomial model for the target
-    utilisation, median of `reps` runs (each build on a reset table)."""
+    utilisation, median of `reps` runs (each build on a reset table). Every status, found flag
+    and hit value of the last run is checked on the device."""
     import torch
     from paper_1710_11246_amd import autotune as A
     from paper_1710_11246_amd import slabhash as S
@@ -688,11 +689,15 @@ def sweep_sizes(log2_sizes=(16, 18, 20, 22, 24), util: float = 0.6, reps: int = 
         a, b = W.hash_params(rng, S.SH_HASH_PRIME)
         B = A.buckets_for_utilisation(n, util)
         t = S.SlabHash(B, A.pool_slabs_for(n, B), a, b)
-        kd, vd = S.to_dev(keys), S.to_dev(W.value_of(keys))
+        vals = W.value_of(keys)
+        kd, vd = S.to_dev(keys), S.to_dev(vals)
         qh, qm = S.to_dev(keys[perm]), S.to_dev(miss)
+        want = S.to_dev(vals[perm])
         st = torch.empty(n, dtype=torch.uint8, device="cuda")
         vo = torch.empty(n, dtype=torch.int32, device="cuda")
         fo = torch.empty(n, dtype=torch.uint8, device="cuda")
+        vm = torch.empty(n, dtype=torch.int32, device="cuda")
+        fm = torch.empty(n, dtype=torch.uint8, device="cuda")
         res = {"build": [], "search_hit": [], "search_miss": []}
         for _ in range(reps + 1):
             t.reset()
@@ -702,12 +707,14 @@ def sweep_sizes(log2_sizes=(16, 18, 20, 22, 24), util: float = 0.6, reps: int = 
             e[1].record()
             S.sh_search(t.handle, qh, vo, fo)
             e[2].record()
-            S.sh_search(t.handle, qm, vo, fo)
+            S.sh_search(t.handle, qm, vm, fm)
             e[3].record()
             torch.cuda.synchronize()
             for i, nm in enumerate(("build", "search_hit", "search_miss")):
                 res[nm].append(e[i].elapsed_time(e[i + 1]))
-        assert bool((st == 1).all())
+        # every insert new, every hit found with its value, every miss absent
+        assert bool((st == 1).all()) and bool((fo == 1).all()) and bool((vo == want).all())
+        assert not bool(fm.any())
         su = t.stats()
         out["2^%d" % k] = {
             "num_buckets": B,
@@ -715,7 +722,7 @@ def sweep_sizes(log2_sizes=(16, 18, 20, 22, 24), util: float = 0.6, reps: int = 
             **{nm + "_Mops": round(n / (float(np.median(v[1:])) * 1e-3) / 1e6, 1)
                for nm, v in res.items()}}
         log("  size 2^%d: %s" % (k, out["2^%d" % k]))
-        del t, kd, vd, qh, qm, st, vo, fo
+        del t, kd, vd, qh, qm, want, st, vo, fo, vm, fm
         torch.cuda.empty_cache()
     return out
 
@@ -810,7 +817,7 @@ def measure_hbm_resident(log2n: int = 26, util: float = 0.6, reps: int = 3,
 def sweep_batches(log2_batches=(15, 16, 17), total: int = 1 << 24, B: int = 793240) -> dict:
     """Incremental insertion ("Incremental insertion"): 2^24 distinct keys inserted in batches of
     each size into a table whose final utilisation is about 0.65; the rate over all batches and
-    over the last eighth of them."""
+    over the last eighth of them. Every insert's status is checked on the device."""
     import torch
     from paper_1710_11246_amd import slabhash as S
     from paper_1710_11246_amd import workload as W
@@ -823,16 +830,17 @@ def sweep_batches(log2_batches=(15, 16, 17), total: int = 1 << 24, B: int = 7932
     for k in log2_batches:
         g = 1 << k
         t.reset()
-        st = torch.empty(g, dtype=torch.uint8, device="cuda")
+        st = torch.empty(total, dtype=torch.uint8, device="cuda")
         evs = []
         for s0 in range(0, total, g):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            S.sh_insert(t.handle, kd[s0:s0 + g], vd[s0:s0 + g], st)
+            S.sh_insert(t.handle, kd[s0:s0 + g], vd[s0:s0 + g], st[s0:s0 + g])
             e1.record()
             evs.append((e0, e1))
         torch.cuda.synchronize()
+        assert bool((st == 1).all())  # every key new
         ms = [x.elapsed_time(y) for x, y in evs]
         tail = ms[-max(1, len(ms) // 8):]
         su = t.stats()
