@@ -96,8 +96,8 @@ typedef struct {
                  once; a value set here is used as given).
    ops_per_wave: operations each wavefront holds at a time, one per lane: 8, 16, 32 or 64
                  (0 = chosen per call: the operation's largest chunk, 16 for inserts and
-                 deletes, 32 for searches, 64 for mixed batches and for tables with flags,
-                 halved while the batch's chunks would not fill the grid; 32 for
+                 deletes, 32 for searches, 64 for mixed batches, whatever the table's
+                 flags, halved while the batch's chunks would not fill the grid; 32 for
                  sh_search_all and sh_delete_all).
    flags:        SH_LAUNCH_COUNTERS makes the operation kernels accumulate the counters that
                  sh_stats reports (off by default: it adds atomics at the end of each kernel). */
