@@ -1577,14 +1577,46 @@ __global__ __launch_bounds__(kBlock) void alloc_kernel(View T, uint64_t n,
 }
 
 // Deallocation: unset each slab's bit in its block's bitmap; entries outside the pool are skipped.
+// The OR of x over the lanes of the wavefront.
+__device__ __forceinline__ uint32_t wave_or(uint32_t x)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+        x |= (uint32_t)__shfl_xor((int)x, d, 64);
+    return x;
+}
+
+// Frees 64 entries per wavefront at a time. Entries that name one bitmap word (slabs handed out
+// together sit in few words) are cleared with one atomic AND by the first of them: up to four
+// such groups per 64 entries, then whatever is left with one AND per entry, so entries spread
+// over many words cost no more than before.
 __global__ __launch_bounds__(kBlock) void free_kernel(View T, const uint32_t *__restrict__ idx,
                                                       uint64_t n)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * kBlock) {
-        const uint32_t f = idx[i];
-        if (pool_in_range(T, f))
-            slab_free(T, f);
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
+    for (uint64_t base = wave * 64; base < n; base += nwaves * 64) {
+        const uint64_t i = base + lane;
+        const uint32_t f = i < n ? idx[i] : kEmpty;
+        bool mine = i < n && pool_in_range(T, f);
+        uint32_t *w = mine ? bitmap_word(T, f) : nullptr;
+        const uint32_t bit = 1u << (f & 31);
+        uint64_t todo = ballot(mine);
+        for (int g = 0; g < 4 && todo; ++g) {
+            const uint32_t lead = ffs0(todo);
+            const uint64_t wa = reinterpret_cast<uint64_t>(w);
+            const uint64_t wl = ((uint64_t)rl((uint32_t)(wa >> 32), lead) << 32) |
+                                rl((uint32_t)wa, lead);
+            const bool same = mine && wa == wl;
+            const uint32_t m = wave_or(same ? bit : 0u);
+            if (lane == lead)
+                __hip_atomic_fetch_and(gmem(w), ~m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            todo &= ~ballot(same);
+            mine = mine && !same;
+        }
+        if (mine)
+            __hip_atomic_fetch_and(gmem(w), ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -114,3 +114,27 @@ def test_whole_pool_and_counters():
     assert np.intersect1d(b, np.setdiff1d(a, gone)).size == 0
     assert t.stats()["pool_allocated"] == n
     assert (alloc(t, 64) == EMPTY).all()
+
+
+def test_free_mixed_patterns():
+    """Frees in one call that mix runs of one bitmap word, scattered slabs and repeated entries:
+    every named slab is free afterwards and no other."""
+    say("case: free runs, scattered and repeated entries")
+    t = S.SlabHash(1, 32 * 2048, 29, 31)
+    a = alloc(t, 50000)
+    assert (a != EMPTY).all() and np.unique(a).size == a.size
+    rng = W.SplitMix64(8)
+    runs = np.sort(a)[:5000]                     # whole words, in order
+    rest = np.setdiff1d(a, runs)
+    scattered = rest[rng.permutation(rest.size)[:7000]]
+    gone = np.concatenate([runs, scattered])
+    listed = np.concatenate([gone, gone[rng.permutation(gone.size)[:3000]]])  # some twice
+    listed = listed[rng.permutation(listed.size)]
+    listed[: 64 * 40] = np.sort(listed[: 64 * 40])  # the first wavefronts see sorted entries
+    S.sh_free_slabs(t.handle, S.to_dev(listed.astype(np.uint32)))
+    assert t.stats()["pool_allocated"] == a.size - gone.size
+    # the freed slabs, and only those, come back
+    b = alloc(t, t.params.pool_slabs - (a.size - gone.size))
+    assert (b != EMPTY).all() and np.unique(b).size == b.size
+    assert np.intersect1d(b, np.setdiff1d(a, gone)).size == 0
+    assert np.intersect1d(b, gone).size == gone.size
