@@ -67,3 +67,100 @@ def test_two_streams_on_one_table(oracle_mod):
     st = assert_same_table(t, o)
     assert st["tombstones"] == half and st["error_word"] == 0
     search_both(t, o, keys)
+
+
+def _updates(rng, n):
+    """Inputs for a table of n built keys k0 (values v0): n fresh keys k1 (values v1), the first
+    quarter of k0 to delete (dk), the second quarter to give new values (rk, rv), and the rest
+    left alone (uk)."""
+    keys = W.unique_keys(rng, 2 * n)
+    k0, k1 = keys[:n], keys[n:]
+    v0, v1 = W.value_of(k0), W.value_of(k1)
+    q = n // 4
+    dk, rk, uk = k0[:q], k0[q:2 * q], k0[2 * q:]
+    rv = (v0[q:2 * q] ^ np.uint32(0x5A5A5A5A)).astype(np.uint32)
+    return k0, v0, k1, v1, dk, rk, rv, uk
+
+
+def test_search_on_another_stream_after_an_event_sees_the_updates(oracle_mod):
+    """Stream A inserts, deletes and replaces; stream B waits for an event recorded after those
+    calls and searches: every update is seen."""
+    say("case: search on stream B after stream A's updates (event order)")
+    rng = W.SplitMix64(1311)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    n = 1 << 17
+    k0, v0, k1, v1, dk, rk, rv, uk = _updates(rng, n)
+    t, o = make(oracle_mod, n // 20, a, b, S.pool_slabs_bound(2 * n))
+    assert bool((t.build(S.to_dev(k0), S.to_dev(v0)) == 1).all())
+    # every device input exists (and stays referenced) before the streams start
+    q = np.concatenate([k1, dk, rk, uk])
+    d_k1, d_v1, d_dk, d_rk, d_rv, dq = (S.to_dev(x) for x in (k1, v1, dk, rk, rv, q))
+    vo = torch.empty(q.size, dtype=torch.int32, device="cuda")
+    fo = torch.empty(q.size, dtype=torch.uint8, device="cuda")
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ready = torch.cuda.Event()
+    ready.record()
+    sa.wait_event(ready)
+    S.sh_insert(t.handle, d_k1, d_v1, None, sa)
+    S.sh_delete(t.handle, d_dk, None, sa)
+    S.sh_insert(t.handle, d_rk, d_rv, None, sa)
+    done_a = torch.cuda.Event()
+    done_a.record(sa)
+    sb.wait_event(done_a)
+    S.sh_search(t.handle, dq, vo, fo, sb)
+    torch.cuda.synchronize()
+    f, v = fo.cpu().numpy(), S.to_host_u32(vo)
+    i1, i2, i3 = k1.size, k1.size + dk.size, k1.size + dk.size + rk.size
+    assert f[:i1].all() and (v[:i1] == v1).all()
+    assert not f[i1:i2].any()
+    assert f[i2:i3].all() and (v[i2:i3] == rv).all()
+    assert f[i3:].all() and (v[i3:] == v0[2 * (n // 4):]).all()
+    o.replace(k0, v0)
+    o.replace(k1, v1)
+    o.delete(dk)
+    o.replace(rk, rv)
+    assert_same_table(t, o)
+
+
+def test_search_concurrent_with_updates_of_the_same_keys(oracle_mod):
+    """Stream B searches while stream A inserts, deletes and replaces the same keys: each search
+    returns its key's state before or after the update that concerns it, never anything else;
+    keys no update touches are exact; afterwards the table equals the oracle's."""
+    say("case: searches concurrent with updates of the same keys")
+    rng = W.SplitMix64(1321)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    n = 1 << 18
+    k0, v0, k1, v1, dk, rk, rv, uk = _updates(rng, n)
+    t, o = make(oracle_mod, n // 20, a, b, S.pool_slabs_bound(2 * n))
+    assert bool((t.build(S.to_dev(k0), S.to_dev(v0)) == 1).all())
+    q = np.concatenate([k1, dk, rk, uk])
+    dq = S.to_dev(q)
+    d_k1, d_v1, d_dk, d_rk, d_rv = (S.to_dev(x) for x in (k1, v1, dk, rk, rv))
+    vo = torch.empty(q.size, dtype=torch.int32, device="cuda")
+    fo = torch.empty(q.size, dtype=torch.uint8, device="cuda")
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ready = torch.cuda.Event()
+    ready.record()
+    sa.wait_event(ready)
+    sb.wait_event(ready)
+    S.sh_insert(t.handle, d_k1, d_v1, None, sa)
+    S.sh_search(t.handle, dq, vo, fo, sb)
+    S.sh_delete(t.handle, d_dk, None, sa)
+    S.sh_insert(t.handle, d_rk, d_rv, None, sa)
+    torch.cuda.synchronize()
+    f, v = fo.cpu().numpy(), S.to_host_u32(vo)
+    i1, i2, i3 = k1.size, k1.size + dk.size, k1.size + dk.size + rk.size
+    # fresh keys: absent, or present with their value
+    assert ((f[:i1] == 0) | ((f[:i1] == 1) & (v[:i1] == v1))).all()
+    # deleted keys: present with the old value, or absent
+    q4 = n // 4
+    assert ((f[i1:i2] == 0) | ((f[i1:i2] == 1) & (v[i1:i2] == v0[:q4]))).all()
+    # replaced keys: present, with the old or the new value
+    assert f[i2:i3].all() and ((v[i2:i3] == v0[q4:2 * q4]) | (v[i2:i3] == rv)).all()
+    # untouched keys: exact
+    assert f[i3:].all() and (v[i3:] == v0[2 * q4:]).all()
+    o.replace(k0, v0)
+    o.replace(k1, v1)
+    o.delete(dk)
+    o.replace(rk, rv)
+    assert_same_table(t, o)
