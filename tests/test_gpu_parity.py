@@ -391,3 +391,69 @@ def test_lost_links_leave_free_slabs_empty(oracle_mod):
     slabs = raw[pool_at:bitmap_at].reshape(pool, 256)
     free_dirty = np.flatnonzero(~allocated & (slabs != 0xFF).any(axis=1))
     assert free_dirty.size == 0, "free pool slabs holding data: %s" % free_dirty[:8]
+
+
+@pytest.mark.parametrize("B", [1, 3])
+def test_boundary_keys_and_values(oracle_mod, B):
+    """Keys at the edges of their range (0, 1, the largest valid key, the keys at and above p,
+    which alias to 0..3 in the hash) with values that share a half with the empty and deleted
+    codes (all ones, 0), among ordinary pairs, on one or three buckets so that lists run over
+    several slabs: inserts, searches, replaces, deletes, re-inserts and a mixed batch all match
+    the oracle."""
+    say("case: boundary keys and values, B=%d" % B)
+    p = S.SH_HASH_PRIME
+    # p + 3 = 0xFFFFFFFE is the largest valid key; every key appears once (the statuses of
+    # repeated keys in one batch depend on the schedule, and another test covers them)
+    edge = np.unique(np.array([0, 1, 2, 3, p - 1, p, p + 1, p + 2, p + 3, 0x7FFFFFFF,
+                               0x80000000], np.uint64)).astype(np.uint32)
+    rng = W.SplitMix64(1501)
+    a, b = W.hash_params(rng, p)
+    other = W.unique_keys(rng, 400)
+    other = other[~np.isin(other, edge)]
+    keys = np.concatenate([edge, other])
+    vals = W.value_of(keys)
+    vals[0::3] = 0xFFFFFFFF                     # value half of the empty code
+    vals[1::3] = 0                              # value half of the deleted code
+    t, o = make(oracle_mod, B, a, b, S.pool_slabs_bound(4 * keys.size))
+    order = rng.permutation(keys.size)
+    st = t.insert(S.to_dev(keys[order]), S.to_dev(vals[order])).cpu().numpy()
+    assert (st == o.replace(keys[order], vals[order])).all()
+    absent = W.unique_keys(rng, 200)
+    absent = absent[~np.isin(absent, keys)]
+    search_both(t, o, np.concatenate([keys, absent]))
+    # replace every edge key's value with all ones, then delete half the keys and re-insert some
+    rv = np.full(edge.size, 0xFFFFFFFF, np.uint32)
+    st = t.insert(S.to_dev(edge), S.to_dev(rv)).cpu().numpy()
+    assert (st == o.replace(edge, rv)).all() and (st == 2).all()
+    dk = keys[order[: keys.size // 2]]
+    ds = t.delete(S.to_dev(dk)).cpu().numpy()
+    assert (ds == o.delete(dk)).all() and (ds == 1).all()
+    back = dk[::2]
+    bv = np.zeros(back.size, np.uint32)
+    st = t.insert(S.to_dev(back), S.to_dev(bv)).cpu().numpy()
+    assert (st == o.replace(back, bv)).all() and (st == 1).all()
+    search_both(t, o, np.concatenate([keys, absent]))
+    # a mixed batch over the same keys: each key appears once, so the outcome is exact
+    mk = np.concatenate([keys, absent[:50]])
+    ops = np.zeros(mk.size, np.uint8)
+    live = ~np.isin(mk, dk[1::2])                # keys present now
+    ops[:keys.size][live[:keys.size] & (np.arange(keys.size) % 3 == 0)] = S.SH_OP_DELETE
+    ops[keys.size:] = S.SH_OP_INSERT             # fresh keys
+    ops[:keys.size][~live[:keys.size]] = S.SH_OP_INSERT  # deleted keys come back
+    mv = W.value_of(mk)
+    mv[::2] = 0xFFFFFFFF
+    vo = torch.empty(mk.size, dtype=torch.int32, device="cuda")
+    so = torch.empty(mk.size, dtype=torch.uint8, device="cuda")
+    S.sh_mixed(t.handle, S.to_dev(ops), S.to_dev(mk), S.to_dev(mv), vo, so)
+    g_st, g_v = so.cpu().numpy(), S.to_host_u32(vo)
+    for i in range(mk.size):
+        k = mk[i:i + 1]
+        if ops[i] == S.SH_OP_INSERT:
+            assert g_st[i] == o.replace(k, mv[i:i + 1])[0]
+        elif ops[i] == S.SH_OP_DELETE:
+            assert g_st[i] == o.delete(k)[0]
+        else:
+            ov, of, _ = o.search(k)
+            assert g_st[i] == of[0] and (not of[0] or g_v[i] == ov[0])
+    assert_same_table(t, o)
+    search_both(t, o, np.concatenate([keys, absent]))
