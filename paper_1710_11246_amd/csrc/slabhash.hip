@@ -514,7 +514,8 @@ __device__ __forceinline__ void slab_free(const View &T, uint32_t idx)
 // either. A chunk is processed in rounds until every op has finished:
 //   1. load: the cursor slab of every unfinished op is read, two ops per load instruction
 //      (lanes 0..31 read op 2q's slab, lanes 32..63 op 2q+1's), all loads issued up front in one
-//      straight run (a pair with no unfinished op reads slab 0).
+//      straight run (a pair with no unfinished op reads slab 0; searches, after their first
+//      round, read only the slabs of pairs still running).
 //   2. decide: the ops are taken in lane order, a pair per step. The wavefront votes on each
 //      slab for the op's key (and, for inserts, for empty slots). The op's slot is the slot
 //      holding the key, else (inserts) the first empty slot, else slot 31, which holds the
@@ -619,8 +620,8 @@ __device__ __forceinline__ uint64_t decide_kv(const uint64_t (&pre)[NQ], uint64_
     const bool by_key = !(Dup && ins) && kslot < 31u;
     // the word of the slab the op needs: its key's value, else the next index
     const uint32_t src = ((lane & 1u) * 32u + (by_key ? kslot : 31u)) * 4u;
-    // (unconditional, so that the fetches are issued back to back; every pair's load read a
-    // valid slab)
+    // (unconditional, so that the fetches are issued back to back; pairs with no running op give
+    // words that no op uses)
     uint32_t hv = 0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -682,6 +683,7 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
     uint32_t rv = kEmpty, rs = 0; // this lane's results
     uint32_t loc = kEmpty;        // this lane's cursor
     uint64_t todo = ballot(act);
+    bool first_round = true;
     while (todo) {
         todo = uniform64(todo);
         ++cnt.rounds;
@@ -690,11 +692,25 @@ __device__ void run_chunk(const View &T, Alloc &al, Counters &cnt, WaveLds &L, C
                                                                      : T.base);
         __builtin_amdgcn_wave_barrier();
         uint64_t pre[NQ];
+        if (K != kSearch || first_round) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const uint64_t *sp = reinterpret_cast<const uint64_t *>(L.p[2 * q + half]);
-            pre[q] = load_slot<kCoherent>(sp + slot);
+            for (int q = 0; q < NQ; ++q) {
+                const uint64_t *sp = reinterpret_cast<const uint64_t *>(L.p[2 * q + half]);
+                pre[q] = load_slot<kCoherent>(sp + slot);
+            }
+        } else {
+            // a search's later rounds usually run a few ops: read only the slabs of pairs still
+            // running
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                pre[q] = 0;
+                if ((todo >> (2 * q)) & 3ull) {
+                    const uint64_t *sp = reinterpret_cast<const uint64_t *>(L.p[2 * q + half]);
+                    pre[q] = load_slot<kCoherent>(sp + slot);
+                }
+            }
         }
+        first_round = false;
         // ---- 2. decide ----
         uint64_t outcome = 0;
         if constexpr (!KO) {
