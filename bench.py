@@ -41,18 +41,18 @@ B_FOR_UTIL = {0.2: 654181, 0.3: 436670, 0.4: 327431, 0.5: 261962, 0.6: 217316, 0
 # Bytes per launch beyond L2 (reads + writes), from rocprofv3 FETCH_SIZE/WRITE_SIZE runs scaled by
 # a 1 GiB device copy; see profiles/slabhash_step_2p22_traffic.md. Valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/slabhash.hip); otherwise reported as null.
-TRAFFIC_SRC_SHA = "c016584e3e09108a"
+TRAFFIC_SRC_SHA = "f87bfcd2f0d57c57"
 # Per launch, from rocprofv3 TCC_HIT_sum/TCC_MISS_sum and TCC_ATOMIC_sum/TCC_EA0_ATOMIC_sum runs
 # of the same source (profiles/slabhash_step_2p22_l2.md): (L2 hit rate, atomics, atomics that
 # reached memory).
-L2_STATS = {"build": (0.3684, 4693625, 4693625), "search_hit": (0.0935, 0, 0),
-            "search_miss": (0.0935, 0, 0), "mixed": (0.3136, 26732, 26732),
-            "reset": (0.5024, 0, 0)}
+L2_STATS = {"build": (0.3683, 4693367, 4693367), "search_hit": (0.0937, 0, 0),
+            "search_miss": (0.0937, 0, 0), "mixed": (0.3127, 26730, 26730),
+            "reset": (0.5023, 0, 0)}
 # The same for the 2^26-key table of measure_hbm_resident (profiles/slabhash_hbm_2p26_traffic.md).
-HBM_TRAFFIC_BYTES = {"build": 22297472665, "search_hit": 17763103395,
-                     "search_miss": 17763103395}
-TRAFFIC_BYTES = {"build": 1349568665, "search_hit": 1039514034, "search_miss": 1039514034,
-                 "mixed": 19521792, "reset": 56247441}
+HBM_TRAFFIC_BYTES = {"build": 22298559292, "search_hit": 17763199906,
+                     "search_miss": 17763199906}
+TRAFFIC_BYTES = {"build": 1349555833, "search_hit": 1039525211, "search_miss": 1039525211,
+                 "mixed": 19521707, "reset": 56247449}
 
 
 def source_sha() -> str:

@@ -91,14 +91,16 @@ typedef struct {
 
 /* Launch shape of the operation kernels. Never changes results.
    waves_per_cu: persistent grid of waves_per_cu * (compute units) wavefronts, at most 64
-                 (0 = the operation's default: 20 for inserts and deletes, 16 otherwise,
-                 lowered to the wavefronts of the chosen kernel that fit on a compute unit at
-                 once; a value set here is used as given).
+                 (0 = the operation's default: 20 for inserts and deletes, 32 for
+                 sh_search_all and sh_delete_all, 16 otherwise, lowered to the wavefronts of
+                 the chosen kernel that fit on a compute unit at once; a value set here is used
+                 as given).
    ops_per_wave: operations each wavefront holds at a time, one per lane: 8, 16, 32 or 64
                  (0 = chosen per call: the operation's largest chunk, 16 for inserts and
                  deletes, 32 for searches, 64 for mixed batches, whatever the table's
-                 flags, halved while the batch's chunks would not fill the grid; 32 for
-                 sh_search_all and sh_delete_all).
+                 flags, halved while the batch's chunks would not fill the grid; 8 for
+                 sh_search_all and sh_delete_all, which by default run up to 32 wavefronts
+                 per CU).
    flags:        SH_LAUNCH_COUNTERS makes the operation kernels accumulate the counters that
                  sh_stats reports (off by default: it adds atomics at the end of each kernel). */
 enum { SH_LAUNCH_COUNTERS = 1u };

@@ -1481,6 +1481,13 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
         uu[lane] = (in && key != kEmpty && !(KO && key == kTombKey))
                        ? bucket_of(key, T.a, T.b, T.B)
                        : 0u;
+        // each op's output range, read once per chunk by the op's own lane (the pairs below
+        // take theirs from that lane)
+        uint64_t my_out0 = 0, my_lim = 0;
+        if (!Del && vout && in) {
+            my_out0 = offsets[base + lane];
+            my_lim = (base + lane + 1 < n) ? offsets[base + lane + 1] : vcap;
+        }
         __builtin_amdgcn_wave_barrier();
         uint64_t pre[NQ];
 #pragma unroll
@@ -1494,9 +1501,13 @@ __global__ __launch_bounds__(kBlock) void all_kernel(View T, const uint32_t *__r
             const uint32_t kq = kk[op];
             bool go = op < count && kq != kEmpty && !(KO && kq == kTombKey);
             uint64_t lim = 0, out0 = 0;
-            if (!Del && vout && go) {
-                out0 = offsets[base + op];
-                lim = (base + op + 1 < n) ? offsets[base + op + 1] : vcap;
+            if (!Del && vout) {
+                const uint32_t lo0 = (uint32_t)__shfl((int)(uint32_t)my_out0, (int)op, 64);
+                const uint32_t hi0 = (uint32_t)__shfl((int)(uint32_t)(my_out0 >> 32), (int)op, 64);
+                const uint32_t lo1 = (uint32_t)__shfl((int)(uint32_t)my_lim, (int)op, 64);
+                const uint32_t hi1 = (uint32_t)__shfl((int)(uint32_t)(my_lim >> 32), (int)op, 64);
+                out0 = ((uint64_t)hi0 << 32) | lo0;
+                lim = ((uint64_t)hi1 << 32) | lo1;
             }
             uint64_t w = pre[q];
             uint64_t *up = T.base + (size_t)uu[op] * 32; // the slab being read
@@ -1968,9 +1979,12 @@ OpsFn ops_fn(const sh_table *t, uint32_t C)
 using AllFn = void (*)(View, const uint32_t *, uint64_t, uint32_t *, const uint64_t *,
                       uint32_t *, uint64_t, uint64_t);
 // SEARCHALL/DELETEALL at C ops per chunk: a straight run of C / 2 loads, one per op pair.
-// 32 ops per chunk by default: 16-load runs at 126 to 130 VGPRs (SEARCHALL) ran 1.6x faster than
-// 32-load runs at 222 to 226 (only 8 wavefronts per CU fit), and DELETEALL 1.25x.
-constexpr uint32_t kAllOps = 32;
+// Each pair's list is then walked on its own, so a wavefront's time goes to dependent latency:
+// by default short chunks (8 ops) and as many wavefronts as fit, up to 32 per CU (2^20 SEARCHALL
+// counts over 4 copies of each key: 83 us at 32 per CU and 8 ops against 116 us at 16 per CU
+// and 32 ops).
+constexpr uint32_t kAllOps = 8;
+constexpr uint32_t kAllWavesPerCU = 32;
 
 template <bool Del, bool KO>
 AllFn all_fn(uint32_t C)
@@ -2297,7 +2311,7 @@ static sh_status_t launch_all(sh_table *t, bool del, const uint32_t *keys, uint6
                          : (ko ? all_fn<false, true>(C) : all_fn<false, false>(C));
     // the default grid is what fits at once at the kernel's register use
     uint64_t waves = (uint64_t)t->num_cu *
-                     launch_wpc(t->waves_per_cu, kDefaultWavesPerCU,
+                     launch_wpc(t->waves_per_cu, kAllWavesPerCU,
                                 reinterpret_cast<const void *>(fn));
     const uint64_t chunks = (n + C - 1) / C;
     if (waves > chunks)
