@@ -807,8 +807,8 @@ def measure_hbm_resident(log2n: int = 26, util: float = 0.6, reps: int = 3,
     # slab reads and swaps from HBM, which the MALL cannot hold)
     pats = measure_patterns(table_bytes, n, reps=3)
     out["access_patterns"] = pats
-    for k, pat in (("build", "load_cas"), ("search_hit", "slab_load"),
-                   ("search_miss", "slab_load")):
+    for k, pat in (("build", "load_cas"), ("search_hit", "search_io"),
+                   ("search_miss", "search_io")):
         out[k]["pattern_ceiling_ms"] = round(pats[pat + "_us"] / 1e3, 4)
         out[k]["frac_of_pattern_ceiling"] = round(pats[pat + "_us"] / 1e3 / out[k]["avg_ms"], 4)
     return out
@@ -1042,18 +1042,31 @@ def measure_alloc(n: int = 1 << 20, reps: int = 5) -> dict:
 
 def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
     """Ceilings of the operation kernels' memory access patterns, from libslabhash_roofs.so, over
-    a buffer of nbytes (the benchmark table's size): n_ops random 256-byte slab reads (the
-    pattern of a search that finds its key in the base slab), n_ops random 64-bit
-    compare-and-swaps, and n_ops slab reads each followed by a compare-and-swap into the slab
-    (the pattern of an insert). Each is the median of `reps` runs at the fastest of 12 launch
-    shapes (8 to 32 wavefronts per CU) and depths (1 to 16 op pairs or swaps in flight per
-    wavefront iteration); the buffer is refilled with all ones before every run."""
+    a buffer of nbytes (the benchmark table's size): n_ops random 256-byte slab reads, n_ops
+    random 64-bit compare-and-swaps, n_ops slab reads each followed by a compare-and-swap into
+    the slab (the pattern of an insert), and n_ops one-slab searches (a key loaded, the slab its
+    mix selects read through the caches, value and flag written: the pattern of a search that
+    ends in its base slab). Each is the median of `reps` runs at the fastest of 12 launch shapes
+    (8 to 32 wavefronts per CU) and depths (1 to 16 op pairs or swaps in flight per wavefront
+    iteration); the buffer is refilled with all ones before every run."""
     import torch
     from paper_1710_11246_amd import roofs as R
     buf = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    keys = torch.randint(-(1 << 31), (1 << 31) - 1, (n_ops,), dtype=torch.int32, device="cuda",
+                         generator=gen)
+    vals = torch.empty(n_ops, dtype=torch.int32, device="cuda")
+    found = torch.empty(n_ops, dtype=torch.uint8, device="cuda")
     res = {"buffer_bytes": buf.numel() * 8, "ops": n_ops}
-    for name, kind in (("slab_load", R.SH_ROOF_SLAB_LOAD), ("cas", R.SH_ROOF_CAS),
-                       ("load_cas", R.SH_ROOF_LOAD_CAS)):
+    runs = (("slab_load", lambda w, d, r: R.sh_roof_run(R.SH_ROOF_SLAB_LOAD, buf, n_ops, w,
+                                                         seed=17 * r + 1, depth=d)),
+            ("cas", lambda w, d, r: R.sh_roof_run(R.SH_ROOF_CAS, buf, n_ops, w, seed=17 * r + 1,
+                                                   depth=d)),
+            ("load_cas", lambda w, d, r: R.sh_roof_run(R.SH_ROOF_LOAD_CAS, buf, n_ops, w,
+                                                        seed=17 * r + 1, depth=d)),
+            ("search_io", lambda w, d, r: R.sh_roof_search(buf, keys, vals, found, w, d)))
+    for name, run in runs:
         best = None
         for wpc in (8, 16, 24, 32):
             for depth in (1, 4, 16):
@@ -1063,7 +1076,7 @@ def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
                     e0.record()
-                    R.sh_roof_run(kind, buf, n_ops, wpc, seed=17 * r + 1, depth=depth)
+                    run(wpc, depth, r)
                     e1.record()
                     torch.cuda.synchronize()
                     if r:
@@ -1074,7 +1087,7 @@ def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
         res[name + "_us"] = round(best[0], 1)
         res[name + "_waves_per_cu"] = best[1]
         res[name + "_depth"] = best[2]
-    del buf
+    del buf, keys, vals, found
     return res
 
 
@@ -1317,7 +1330,7 @@ def main():
         log("access-pattern ceilings")
         patterns = measure_patterns(int(table.storage.numel()), N_KEYS)
         # each kernel against the ceiling of its own access pattern, measured above
-        pattern_of = {"build": "load_cas", "search_hit": "slab_load", "search_miss": "slab_load"}
+        pattern_of = {"build": "load_cas", "search_hit": "search_io", "search_miss": "search_io"}
         for k, pat in pattern_of.items():
             kernels[k]["pattern_ceiling_us"] = patterns[pat + "_us"]
             kernels[k]["frac_of_pattern_ceiling"] = round(patterns[pat + "_us"] /

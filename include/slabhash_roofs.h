@@ -18,6 +18,12 @@
  *
  * The compare-and-swap patterns overwrite the words they win; fill the buffer with 0xFF bytes
  * before each timed run so every run starts from empty slots.
+ *
+ * sh_roof_search is the memory pattern of a search whose every list is one slab ("Search": one
+ * slab read per operation), with the query and result streams: op i loads d_keys[i], reads
+ * slab mix(d_keys[i]) scaled into [0, slabs) through the caches (half a wavefront, 8 bytes per
+ * lane), and writes the high word of the first of slots 0..30 whose low word equals the key to
+ * d_vals_out[i] (all ones if none) and 1/0 to d_found[i]. It reads the buffer only.
  */
 #ifndef SLABHASH_ROOFS_H
 #define SLABHASH_ROOFS_H
@@ -46,6 +52,18 @@ enum { SH_ROOF_SLAB_LOAD = 0, SH_ROOF_CAS = 1, SH_ROOF_LOAD_CAS = 2 };
    or the launch fails, else SH_OK. */
 sh_status_t sh_roof_run(int kind, void *d_buf, size_t bytes, uint64_t n_ops,
                         uint32_t waves_per_cu, uint32_t depth, uint32_t seed, void *stream);
+
+/* Enqueue n_ops one-slab searches (above) over d_buf on `stream`; asynchronous.
+   d_buf, bytes, n_ops, waves_per_cu: as for sh_roof_run; the buffer is not written.
+   d_keys:       n_ops keys (device, caller-owned); any 32-bit values.
+   d_vals_out:   n_ops values out; d_found: n_ops flags out (device, caller-owned).
+   depth:        op pairs whose slab loads are issued before any is used: 1, 4, 8 or 16 (0 = 8);
+                 a wavefront takes 2 * depth ops per iteration.
+   Returns SH_EINVAL for a bad argument or, with n_ops > 0, a NULL array (nothing enqueued),
+   SH_EHIP if the device query or the launch fails, else SH_OK. */
+sh_status_t sh_roof_search(const void *d_buf, size_t bytes, const uint32_t *d_keys,
+                           uint64_t n_ops, uint32_t *d_vals_out, uint8_t *d_found,
+                           uint32_t waves_per_cu, uint32_t depth, void *stream);
 
 #ifdef __cplusplus
 }

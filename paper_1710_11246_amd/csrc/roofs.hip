@@ -1,7 +1,8 @@
 // Microbenchmarks of the slab hash's memory access patterns (random slab reads, random 64-bit
-// compare-and-swaps, and a slab read followed by a compare-and-swap into it), measuring the
-// ceilings the operation kernels run against. Every address is slab * 32 + word with
-// slab < slabs and word < 32, inside the caller's buffer.
+// compare-and-swaps, a slab read followed by a compare-and-swap into it, and a search whose
+// lists are all one slab long), measuring the ceilings the operation kernels run against.
+// Every address is slab * 32 + word with slab < slabs and word < 32, inside the caller's
+// buffer.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -101,6 +102,59 @@ __global__ __launch_bounds__(kBlock) void cas_kernel(uint64_t *buf, uint32_t sla
     sink(buf, acc);
 }
 
+// A search whose every list is one slab: 2P ops per wavefront iteration. Lanes 0..2P-1 load the
+// iteration's keys (one coalesced load); op 2j + h's slab, chosen by a fixed mix of its key, is
+// read through the caches by half h (lanes 32h..32h+31) for each pair j, all P loads issued
+// before any is used; each half votes on slots 0..30 for its key, and lane 2j + h of the
+// iteration writes op 2j + h's value (the high word of the first matching slot, else all ones)
+// and found flag, so the results leave in one coalesced store each.
+template <int P>
+__global__ __launch_bounds__(kBlock) void search_kernel(const uint64_t *__restrict__ buf,
+                                                        uint32_t slabs,
+                                                        const uint32_t *__restrict__ keys,
+                                                        uint32_t n, uint32_t *__restrict__ vout,
+                                                        uint8_t *__restrict__ found)
+{
+    constexpr uint32_t G = 2 * P; // ops per iteration, at most 32
+    const uint32_t lane = threadIdx.x & 63u, half = lane >> 5, slot = lane & 31u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t groups = (uint32_t)(((uint64_t)n + G - 1) / G);
+    for (uint32_t g = wave; g < groups; g += nwaves) {
+        const uint64_t base = (uint64_t)g * G;
+        const bool in = lane < G && base + lane < n;
+        const uint32_t k = in ? keys[base + lane] : 0u;
+        uint64_t w[P];
+        uint32_t kq[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            kq[j] = (uint32_t)__shfl((int)k, 2 * j + (int)half, 64);
+            const uint32_t s = __umulhi(mix(kq[j]), slabs);
+            w[j] = buf[(size_t)s * 32 + slot];
+        }
+        uint32_t my_v = ~0u, my_f = 0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const uint64_t m = __ballot(slot < 31 && (uint32_t)w[j] == kq[j]);
+            const uint32_t hm = (uint32_t)(m >> (lane & 32u));
+            const uint32_t src = (lane & 32u) | (hm ? (uint32_t)__builtin_ctz(hm) : 0u);
+            const uint32_t hv = (uint32_t)__shfl((int)(uint32_t)(w[j] >> 32), (int)src, 64);
+            const uint32_t v = hm ? hv : ~0u;
+            // lane 2j + h takes half h's result: v is uniform within each half
+            const uint32_t vv = (uint32_t)__shfl((int)v, (int)((lane & 1u) << 5), 64);
+            const uint32_t ff = (uint32_t)__shfl((int)(hm != 0), (int)((lane & 1u) << 5), 64);
+            if ((lane >> 1) == (uint32_t)j) {
+                my_v = vv;
+                my_f = ff;
+            }
+        }
+        if (in) {
+            vout[base + lane] = my_v;
+            found[base + lane] = (uint8_t)my_f;
+        }
+    }
+}
+
 template <int P>
 void launch_pattern(int kind, dim3 grid, hipStream_t s, uint64_t *buf, uint32_t slabs, uint32_t n,
                     uint32_t seed)
@@ -148,6 +202,48 @@ extern "C" sh_status_t sh_roof_run(int kind, void *d_buf, size_t bytes, uint64_t
         break;
     default:
         launch_pattern<16>(kind, dim3(blocks), s, buf, slabs, n, seed);
+        break;
+    }
+    return hipGetLastError() == hipSuccess ? SH_OK : SH_EHIP;
+}
+
+extern "C" sh_status_t sh_roof_search(const void *d_buf, size_t bytes, const uint32_t *d_keys,
+                                      uint64_t n_ops, uint32_t *d_vals_out, uint8_t *d_found,
+                                      uint32_t waves_per_cu, uint32_t depth, void *stream)
+{
+    if (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 255u) || bytes < 256 || (bytes & 255u) ||
+        bytes / 256 > 0xFFFFFFFFull || n_ops >= (1ull << 32) - 64 || waves_per_cu > 64 ||
+        (depth != 0 && depth != 1 && depth != 4 && depth != 8 && depth != 16) ||
+        (n_ops && (!d_keys || !d_vals_out || !d_found)))
+        return SH_EINVAL;
+    if (n_ops == 0)
+        return SH_OK;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+        return SH_EHIP;
+    const uint32_t wpc = waves_per_cu ? waves_per_cu : 32u;
+    const dim3 grid(((uint32_t)ncu * wpc + 3u) / 4u); // four wavefronts per block
+    const uint64_t *buf = static_cast<const uint64_t *>(d_buf);
+    const uint32_t slabs = (uint32_t)(bytes / 256), n = (uint32_t)n_ops;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    switch (depth ? depth : 8u) {
+    case 1:
+        hipLaunchKernelGGL(search_kernel<1>, grid, dim3(kBlock), 0, s, buf, slabs, d_keys, n,
+                           d_vals_out, d_found);
+        break;
+    case 4:
+        hipLaunchKernelGGL(search_kernel<4>, grid, dim3(kBlock), 0, s, buf, slabs, d_keys, n,
+                           d_vals_out, d_found);
+        break;
+    case 8:
+        hipLaunchKernelGGL(search_kernel<8>, grid, dim3(kBlock), 0, s, buf, slabs, d_keys, n,
+                           d_vals_out, d_found);
+        break;
+    default:
+        hipLaunchKernelGGL(search_kernel<16>, grid, dim3(kBlock), 0, s, buf, slabs, d_keys, n,
+                           d_vals_out, d_found);
         break;
     }
     return hipGetLastError() == hipSuccess ? SH_OK : SH_EHIP;

@@ -132,8 +132,8 @@ def test_roofs_library_exports_and_argument_errors():
         __graft_entry__.build()
     rl = R.lib()
     declared = R.declared_symbols()
-    assert declared == ["sh_roof_run"] and set(declared) == set(R._SIGS)
-    assert hasattr(rl, "sh_roof_run")
+    assert declared == ["sh_roof_run", "sh_roof_search"] and set(declared) == set(R._SIGS)
+    assert hasattr(rl, "sh_roof_run") and hasattr(rl, "sh_roof_search")
     buf = ctypes.c_void_p(1 << 20)  # aligned stand-in; every call below fails before using it
     bad = [(7, buf, 1 << 20, 10, 0, 0), (-1, buf, 1 << 20, 10, 0, 0),
            (0, None, 1 << 20, 10, 0, 0), (0, ctypes.c_void_p((1 << 20) + 8), 1 << 20, 10, 0, 0),
@@ -144,6 +144,15 @@ def test_roofs_library_exports_and_argument_errors():
         assert rl.sh_roof_run(kind, p, nbytes, n, wpc, depth, 1, None) == S.SH_EINVAL
     # no operations: nothing is enqueued and no device is touched
     assert rl.sh_roof_run(1, buf, 1 << 20, 0, 0, 0, 1, None) == S.SH_OK
+    arr = ctypes.c_void_p(1 << 24)  # stand-in key and result arrays, never used either
+    bad = [(None, 1 << 20, arr, 10, arr, arr, 0, 0), (ctypes.c_void_p((1 << 20) + 8), 1 << 20,
+           arr, 10, arr, arr, 0, 0), (buf, 300, arr, 10, arr, arr, 0, 0),
+           (buf, 1 << 20, arr, (1 << 32) - 64, arr, arr, 0, 0), (buf, 1 << 20, None, 10, arr, arr,
+           0, 0), (buf, 1 << 20, arr, 10, None, arr, 0, 0), (buf, 1 << 20, arr, 10, arr, None, 0,
+           0), (buf, 1 << 20, arr, 10, arr, arr, 65, 0), (buf, 1 << 20, arr, 10, arr, arr, 0, 2)]
+    for p, nbytes, k, n, v, f, wpc, depth in bad:
+        assert rl.sh_roof_search(p, nbytes, k, n, v, f, wpc, depth, None) == S.SH_EINVAL
+    assert rl.sh_roof_search(buf, 1 << 20, None, 0, None, None, 0, 0, None) == S.SH_OK
 
 
 def test_bench_refuses_more_than_one_gpu():

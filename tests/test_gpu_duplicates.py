@@ -126,6 +126,40 @@ def test_list_order_across_batches(oracle_mod, opw):
     assert not f.cpu().numpy().any()
 
 
+@pytest.mark.parametrize("opw", [0, 64])
+def test_search_all_output_ranges(oracle_mod, opw):
+    """SEARCHALL into ranges the caller chose: query i writes its values in list order from
+    offsets[i], never past offsets[i + 1] nor the output's capacity, and nothing else; the counts
+    are the full counts whatever the room. Ranges here leave gaps, cut lists short, are empty,
+    and run past the capacity at the end."""
+    say("case: SEARCHALL into caller ranges, %d ops per wavefront" % opw)
+    t, o, rng = make_dup(oracle_mod, 97, S.pool_slabs_bound(20000), 960)
+    t.set_launch(0, opw)
+    keys = W.unique_keys(rng, 3500)
+    present, absent = keys[:3000], keys[3000:]
+    for r in range(4):
+        v = (W.value_of(present) + np.uint32(r)).astype(np.uint32)
+        assert bool((t.insert(S.to_dev(present), S.to_dev(v)) == 1).all())
+        o.replace(present, v)
+    q = np.concatenate([present, absent])[rng.permutation(keys.size)]
+    oc, ooff, ov = o.search_all(q)
+    room = np.array([0, 1, 2, 3, 4, 6], np.int64)[rng.below(q.size, 6).astype(np.int64)]
+    offsets = np.zeros(q.size, np.int64)
+    offsets[1:] = np.cumsum(room[:-1])
+    cap = int(room.sum()) - 37  # the last queries' ranges run past the output
+    sentinel = np.uint32(0xDEADBEEF)
+    out = S.to_dev(np.full(cap, sentinel, np.uint32))
+    counts = torch.empty(q.size, dtype=torch.int32, device="cuda")
+    S.sh_search_all(t.handle, S.to_dev(q), counts, torch.from_numpy(offsets).cuda(), out)
+    assert (counts.cpu().numpy() == oc).all()
+    want = np.full(cap, sentinel, np.uint32)
+    for i in range(q.size):
+        end = min(int(offsets[i + 1]) if i + 1 < q.size else cap, cap)
+        k = max(0, min(int(oc[i]), end - int(offsets[i])))
+        want[offsets[i]:offsets[i] + k] = ov[ooff[i]:ooff[i] + k]
+    assert (S.to_host_u32(out) == want).all()
+
+
 def test_mixed_batch_with_duplicates(oracle_mod):
     """Inserts, deletes and searches on disjoint key roles in one concurrent batch. The storage
     is checked on the host (host_walk) after the base build and after the batch, before any

@@ -1,5 +1,6 @@
 """GPU checks of the access-pattern microbenchmarks: the compare-and-swap patterns write exactly
-where their documented addressing says, and the slab-read pattern leaves the buffer unchanged."""
+where their documented addressing says, the slab-read pattern leaves the buffer unchanged, and the
+one-slab search returns what its documented addressing and vote give."""
 import numpy as np
 import pytest
 import torch
@@ -70,3 +71,48 @@ def test_slab_load_pattern_reads_only():
     R.sh_roof_run(R.SH_ROOF_SLAB_LOAD, buf, 1 << 16, 0, 3)
     torch.cuda.synchronize()
     assert torch.equal(buf, ref)
+
+
+@pytest.mark.parametrize("depth", [1, 16])
+def test_one_slab_search_pattern(depth):
+    """Keys planted in the slab their mix selects (some twice, the first copy deciding; some in
+    slot 31, which is never voted on) and keys nowhere: values and flags as documented, the
+    buffer unchanged, for a ragged number of ops."""
+    slabs, n = 1031, 5001
+    rng = np.random.default_rng(4242 + depth)
+    words = rng.integers(0, 1 << 63, size=(slabs, 32), dtype=np.int64).view(np.uint64)
+    keys = rng.choice(np.uint64(1) << np.uint64(32), size=n, replace=False).astype(np.uint64)
+    keys = keys[keys != 0xFFFFFFFF]
+    n = keys.size
+    slab = (mix(keys) * slabs) >> 32
+    # no stray match: clear every low word that equals one of the keys
+    lo = words & np.uint64(0xFFFFFFFF)
+    words[np.isin(lo, keys)] ^= np.uint64(1)
+    want_v = np.full(n, 0xFFFFFFFF, np.uint64)
+    want_f = np.zeros(n, np.uint8)
+    for i in range(0, n, 3):                       # a third of the keys are planted
+        s_, k = int(slab[i]), keys[i]
+        slot = int(rng.integers(0, 32))
+        hi = np.uint64(int(rng.integers(0, 1 << 32)))
+        words[s_, slot] = (hi << np.uint64(32)) | k
+        if slot < 31:
+            want_v[i], want_f[i] = hi, 1
+            if slot < 30 and i % 2 == 0:          # a later copy does not change the result
+                words[s_, slot + 1] = (np.uint64(7) << np.uint64(32)) | k
+    # a plant can overwrite an earlier one in the same slab: recompute from the final words
+    for i in range(0, n, 3):
+        row = words[int(slab[i])]
+        hit = np.flatnonzero((row[:31] & np.uint64(0xFFFFFFFF)) == keys[i])
+        want_v[i] = (row[hit[0]] >> np.uint64(32)) if hit.size else np.uint64(0xFFFFFFFF)
+        want_f[i] = 1 if hit.size else 0
+    buf = torch.from_numpy(words.view(np.int64).reshape(-1).copy()).cuda()
+    ref = buf.clone()
+    kd = torch.from_numpy(keys.astype(np.uint32).view(np.int32)).cuda()
+    vals = torch.empty(n, dtype=torch.int32, device="cuda")
+    found = torch.empty(n, dtype=torch.uint8, device="cuda")
+    R.sh_roof_search(buf, kd, vals, found, 4, depth)
+    torch.cuda.synchronize()
+    assert torch.equal(buf, ref)
+    assert (found.cpu().numpy() == want_f).all() and int(want_f.sum()) > n // 4
+    assert (vals.cpu().numpy().view(np.uint32) == want_v.astype(np.uint32)).all()
+
