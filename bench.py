@@ -633,6 +633,8 @@ def measure_config1(reps: int = 20) -> dict:
     ds = torch.empty(dd.numel(), dtype=torch.uint8, device="cuda")
     vo = torch.empty(n, dtype=torch.int32, device="cuda")
     fo = torch.empty(n, dtype=torch.uint8, device="cuda")
+    vo2 = torch.empty(n, dtype=torch.int32, device="cuda")
+    fo2 = torch.empty(n, dtype=torch.uint8, device="cuda")
     names = ("build", "search", "delete", "search_after")
     res = {k: [] for k in names}
     first = None
@@ -644,13 +646,12 @@ def measure_config1(reps: int = 20) -> dict:
         e[1].record()
         S.sh_search(t.handle, qd, vo, fo)
         e[2].record()
-        f1 = fo.clone()
         S.sh_delete(t.handle, dd, ds)
         e[3].record()
-        S.sh_search(t.handle, qd, vo, fo)
+        S.sh_search(t.handle, qd, vo2, fo2)
         e[4].record()
         torch.cuda.synchronize()
-        outs = (st.clone(), f1, ds.clone(), fo.clone(), vo.clone())
+        outs = (st.clone(), fo.clone(), vo.clone(), ds.clone(), fo2.clone(), vo2.clone())
         if first is None:
             first = outs
         assert all(bool((a == b).all()) for a, b in zip(outs, first))
@@ -757,6 +758,8 @@ def measure_hbm_resident(log2n: int = 26, util: float = 0.6, reps: int = 3,
     st = torch.empty(n, dtype=torch.uint8, device="cuda")
     vo = torch.empty(n, dtype=torch.int32, device="cuda")
     fo = torch.empty(n, dtype=torch.uint8, device="cuda")
+    vm = torch.empty(n, dtype=torch.int32, device="cuda")
+    fm = torch.empty(n, dtype=torch.uint8, device="cuda")
     names = ("build", "search_hit", "search_miss")
     res = {k: [] for k in names}
     for rep in range(reps + 1):
@@ -767,11 +770,12 @@ def measure_hbm_resident(log2n: int = 26, util: float = 0.6, reps: int = 3,
         e[1].record()
         S.sh_search(t.handle, qh, vo, fo)
         e[2].record()
-        ok_hit = bool((fo == 1).all()) and bool((vo == want).all())
-        S.sh_search(t.handle, qm, vo, fo)
+        S.sh_search(t.handle, qm, vm, fm)
         e[3].record()
         torch.cuda.synchronize()
-        assert bool((st == 1).all()) and ok_hit and not bool(fo.any())
+        # checked after the timed span, so that no check runs between the events
+        assert bool((st == 1).all()) and bool((fo == 1).all()) and bool((vo == want).all())
+        assert not bool(fm.any())
         if rep:
             for i, k in enumerate(names):
                 res[k].append(e[i].elapsed_time(e[i + 1]))
@@ -801,7 +805,7 @@ def measure_hbm_resident(log2n: int = 26, util: float = 0.6, reps: int = 3,
                   "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
                   "traffic_bytes": HBM_TRAFFIC_BYTES.get(k) if traffic_ok else None}
     table_bytes = int(t.storage.numel())
-    del t, kd, vd, qh, qm, want, st, vo, fo
+    del t, kd, vd, qh, qm, want, st, vo, fo, vm, fm
     torch.cuda.empty_cache()
     # the same access patterns' ceilings over a buffer of the table's size (random 256-byte
     # slab reads and swaps from HBM, which the MALL cannot hold)
