@@ -5,7 +5,9 @@
     table's contents;
   - the served form on a resident 2^24-key table under Poisson arrivals with Zipf-shared keys:
     real-time linearizability of every search, and the final table equal to the oracle's;
-  - the bulk build and both searches of 2^22 keys at every bucket count of the utilisation sweep.
+  - the bulk build and both searches of 2^22 keys at every bucket count of the utilisation sweep;
+  - the HBM-resident 2^26-key build and searches: every search result exact, and every bucket's
+    live, deleted and slab counts equal to what the oracle's hash and the slab capacity give.
 """
 import sys
 
@@ -161,3 +163,44 @@ def test_served_2p24_real_time(oracle_mod):
     o.mixed(sr.ops, sr.keys, sr.vals)
     say("  comparing the final table")
     assert_same_table(t, o)
+
+
+def test_hbm_resident_2p26(oracle_mod):
+    """The benchmark's 2^26-key workload (bulk build at utilisation 0.6, then 2^26 all-hit and
+    2^26 all-miss searches) in its launch configuration. Buckets are independent, so the whole
+    table is pinned without a 2^26-entry oracle: each bucket's live count is the number of keys
+    the oracle's hash sends there, its slab count max(1, ceil(live / 31)) (a build fills slabs in
+    order), no deleted slots, the pool holding exactly the overflow slabs; every hit returns its
+    key's value and every miss is absent."""
+    say("case: HBM-resident build and searches, n=2^26")
+    n, seed = 1 << 26, 61
+    keys = W.distinct_keys(seed, 0, n)
+    miss = W.distinct_keys(seed, n, n)
+    perm = W.SplitMix64(seed + 1).permutation(n)
+    a, b = W.hash_params(W.SplitMix64(seed + 2), S.SH_HASH_PRIME)
+    B = A.buckets_for_utilisation(n, 0.6)
+    t = S.SlabHash(B, A.pool_slabs_for(n, B), a, b)
+    vals = W.value_of(keys)
+    st = t.build(S.to_dev(keys), S.to_dev(vals))
+    assert bool((st == 1).all())
+    qh = keys[perm]
+    v, f = t.search(S.to_dev(qh))
+    assert bool((f == 1).all()) and (S.to_host_u32(v) == vals[perm]).all()
+    del v, f
+    v, f = t.search(S.to_dev(miss))
+    assert not bool(f.any()) and bool((v == -1).all())
+    del v, f
+    counts = torch.empty(3 * B, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    viol = torch.zeros(1, dtype=torch.int32, device="cuda")
+    S.sh_dump(t.handle, None, None, None, counts, cnt, viol)
+    c = S.to_host_u32(counts).reshape(-1, 3).astype(np.int64)
+    assert int(viol.item()) == 0 and int(cnt.item()) == n
+    live = np.bincount(oracle_mod.Oracle(B, M, a, b).bucket_of(keys).astype(np.int64),
+                       minlength=B)
+    assert (c[:, 0] == live).all() and not c[:, 1].any()
+    assert (c[:, 2] == np.maximum(1, (live + M - 1) // M)).all()
+    su = t.stats()
+    assert su["pool_allocated"] == int((c[:, 2] - 1).sum()) and su["violations"] == 0
+    assert su["live"] == n and su["error_word"] == 0
+

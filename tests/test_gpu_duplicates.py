@@ -160,6 +160,47 @@ def test_search_all_output_ranges(oracle_mod, opw):
     assert (S.to_host_u32(out) == want).all()
 
 
+def test_duplicates_at_benchmark_size(oracle_mod):
+    """The benchmark's duplicates workload at its own size, against the oracle: 2^20 keys, four
+    copies each, one copy per insert batch of 2^20, into 217,316 buckets; SEARCH returns each
+    key's first copy, SEARCHALL all four values in batch order (into ranges offset by 4, as the
+    benchmark sizes them), DELETE takes the first copy and DELETEALL the other three, the table
+    equal to the oracle's after each step. The default launch shapes, as the benchmark runs."""
+    say("case: duplicates at the benchmark's size (2^20 keys x 4 copies, B=217316)")
+    n, copies, B = 1 << 20, 4, 217316
+    keys = W.distinct_keys(81, 0, n)
+    rng = W.SplitMix64(83)
+    a, b = W.hash_params(rng, S.SH_HASH_PRIME)
+    t = S.SlabHash(B, S.pool_slabs_bound(copies * n), a, b, duplicates=True)
+    o = oracle_mod.Oracle(B, M, a, b, duplicates=True)
+    kd = S.to_dev(keys)
+    for c in range(copies):
+        v = (W.value_of(keys) + np.uint32(c)).astype(np.uint32)
+        assert bool((t.insert(kd, S.to_dev(v)) == 1).all())
+        o.replace(keys, v)
+    assert_same_table(t, o)
+    q = keys[W.SplitMix64(82).below(copies * n, n)]
+    gv, gf = t.search(S.to_dev(q))
+    assert bool((gf == 1).all()) and (S.to_host_u32(gv) == W.value_of(q)).all()
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    off = torch.arange(0, copies * n, copies, dtype=torch.int64, device="cuda")
+    vals = torch.empty(copies * n, dtype=torch.int32, device="cuda")
+    S.sh_search_all(t.handle, kd, cnt, off, vals)
+    oc, ooff, ov = o.search_all(keys)
+    assert (cnt.cpu().numpy() == copies).all() and (oc == copies).all()
+    assert (S.to_host_u32(vals) == ov).all()
+    want = (W.value_of(keys)[:, None] + np.arange(copies, dtype=np.uint32)).astype(np.uint32)
+    assert (ov.reshape(n, copies) == want).all()  # batch order, pinned without the oracle
+    assert bool((t.delete(kd) == 1).all())
+    o.delete(keys)
+    assert_same_table(t, o)
+    c = t.delete_all(kd).cpu().numpy()
+    assert (c == copies - 1).all() and (o.delete_all(keys) == copies - 1).all()
+    assert_same_table(t, o)
+    _, gf = t.search(kd)
+    assert not gf.cpu().numpy().any()
+
+
 def test_mixed_batch_with_duplicates(oracle_mod):
     """Inserts, deletes and searches on disjoint key roles in one concurrent batch. The storage
     is checked on the host (host_walk) after the base build and after the batch, before any
