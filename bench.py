@@ -811,7 +811,7 @@ def measure_hbm_resident(log2n: int = 26, util: float = 0.6, reps: int = 3,
     # slab reads and swaps from HBM, which the MALL cannot hold)
     pats = measure_patterns(table_bytes, n, reps=3)
     out["access_patterns"] = pats
-    for k, pat in (("build", "load_cas"), ("search_hit", "search_io"),
+    for k, pat in (("build", "insert_io"), ("search_hit", "search_io"),
                    ("search_miss", "search_io")):
         out[k]["pattern_ceiling_ms"] = round(pats[pat + "_us"] / 1e3, 4)
         out[k]["frac_of_pattern_ceiling"] = round(pats[pat + "_us"] / 1e3 / out[k]["avg_ms"], 4)
@@ -1048,9 +1048,11 @@ def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
     """Ceilings of the operation kernels' memory access patterns, from libslabhash_roofs.so, over
     a buffer of nbytes (the benchmark table's size): n_ops random 256-byte slab reads, n_ops
     random 64-bit compare-and-swaps, n_ops slab reads each followed by a compare-and-swap into
-    the slab (the pattern of an insert), and n_ops one-slab searches (a key loaded, the slab its
-    mix selects read through the caches, value and flag written: the pattern of a search that
-    ends in its base slab). Each is the median of `reps` runs at the fastest of 12 launch shapes
+    the slab, n_ops one-slab searches (a key loaded, the slab its mix selects read through the
+    caches, value and flag written: the pattern of a search that ends in its base slab), and
+    n_ops one-slab inserts (a key and value loaded, the slab read coherently, the pair swapped
+    into its first empty slot, a status written: the pattern of an insert of an absent key
+    into a base slab with room). Each is the median of `reps` runs at the fastest of 12 launch shapes
     (8 to 32 wavefronts per CU) and depths (1 to 16 op pairs or swaps in flight per wavefront
     iteration); the buffer is refilled with all ones before every run."""
     import torch
@@ -1069,7 +1071,8 @@ def measure_patterns(nbytes: int, n_ops: int, reps: int = 5) -> dict:
                                                    depth=d)),
             ("load_cas", lambda w, d, r: R.sh_roof_run(R.SH_ROOF_LOAD_CAS, buf, n_ops, w,
                                                         seed=17 * r + 1, depth=d)),
-            ("search_io", lambda w, d, r: R.sh_roof_search(buf, keys, vals, found, w, d)))
+            ("search_io", lambda w, d, r: R.sh_roof_search(buf, keys, vals, found, w, d)),
+            ("insert_io", lambda w, d, r: R.sh_roof_insert(buf, keys, vals, found, w, d)))
     for name, run in runs:
         best = None
         for wpc in (8, 16, 24, 32):
@@ -1334,7 +1337,7 @@ def main():
         log("access-pattern ceilings")
         patterns = measure_patterns(int(table.storage.numel()), N_KEYS)
         # each kernel against the ceiling of its own access pattern, measured above
-        pattern_of = {"build": "load_cas", "search_hit": "search_io", "search_miss": "search_io"}
+        pattern_of = {"build": "insert_io", "search_hit": "search_io", "search_miss": "search_io"}
         for k, pat in pattern_of.items():
             kernels[k]["pattern_ceiling_us"] = patterns[pat + "_us"]
             kernels[k]["frac_of_pattern_ceiling"] = round(patterns[pat + "_us"] /

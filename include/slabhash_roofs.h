@@ -24,6 +24,13 @@
  * slab mix(d_keys[i]) scaled into [0, slabs) through the caches (half a wavefront, 8 bytes per
  * lane), and writes the high word of the first of slots 0..30 whose low word equals the key to
  * d_vals_out[i] (all ones if none) and 1/0 to d_found[i]. It reads the buffer only.
+ *
+ * sh_roof_insert is the memory pattern of an insert whose key is absent and whose base slab has
+ * room ("Insertion"), with its input and status streams: op i loads d_keys[i] and d_vals[i],
+ * reads slab mix(d_keys[i]) scaled into [0, slabs) with device-coherent loads (half a
+ * wavefront, 8 bytes per lane), swaps the pair (value in the high word) into the first
+ * all-ones slot of 0..30 (slot 0 if none), expecting all ones, and writes 1 to d_status[i] if
+ * the swap won, else 0. Fill the buffer with 0xFF bytes before each timed run.
  */
 #ifndef SLABHASH_ROOFS_H
 #define SLABHASH_ROOFS_H
@@ -63,6 +70,16 @@ sh_status_t sh_roof_run(int kind, void *d_buf, size_t bytes, uint64_t n_ops,
    SH_EHIP if the device query or the launch fails, else SH_OK. */
 sh_status_t sh_roof_search(const void *d_buf, size_t bytes, const uint32_t *d_keys,
                            uint64_t n_ops, uint32_t *d_vals_out, uint8_t *d_found,
+                           uint32_t waves_per_cu, uint32_t depth, void *stream);
+
+/* Enqueue n_ops one-slab inserts (above) over d_buf on `stream`; asynchronous.
+   d_buf, bytes, n_ops, waves_per_cu, depth: as for sh_roof_search; the buffer is written.
+   d_keys, d_vals: n_ops keys and values (device, caller-owned).
+   d_status:     n_ops statuses out (device, caller-owned).
+   Returns SH_EINVAL for a bad argument or, with n_ops > 0, a NULL array (nothing enqueued),
+   SH_EHIP if the device query or the launch fails, else SH_OK. */
+sh_status_t sh_roof_insert(void *d_buf, size_t bytes, const uint32_t *d_keys,
+                           const uint32_t *d_vals, uint64_t n_ops, uint8_t *d_status,
                            uint32_t waves_per_cu, uint32_t depth, void *stream);
 
 #ifdef __cplusplus

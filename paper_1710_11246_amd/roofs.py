@@ -24,6 +24,9 @@ _SIGS = {
     "sh_roof_search": ([ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_uint64,
                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                         ctypes.c_void_p], ctypes.c_int),
+    "sh_roof_insert": ([ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                        ctypes.c_void_p], ctypes.c_int),
 }
 _lib = None
 
@@ -86,3 +89,27 @@ def sh_roof_search(buf: torch.Tensor, keys: torch.Tensor, vals: torch.Tensor, fo
                                 ctypes.c_void_p(_stream(stream)))
     if code != SH_OK:
         raise SlabHashError("sh_roof_search", code)
+
+
+def sh_roof_insert(buf: torch.Tensor, keys: torch.Tensor, vals: torch.Tensor,
+                   status: torch.Tensor, waves_per_cu: int = 0, depth: int = 0,
+                   stream=None) -> None:
+    """Enqueue keys.numel() one-slab inserts over the device tensor `buf` (its bytes, rounded
+    down to whole 256-byte slabs): status (uint8) receives 1 where the op's swap won."""
+    if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.is_contiguous()):
+        raise ValueError("buf must be a contiguous device tensor")
+    n = keys.numel()
+    for name, x, dts in (("keys", keys, (torch.int32, torch.uint32)),
+                         ("vals", vals, (torch.int32, torch.uint32)),
+                         ("status", status, (torch.uint8,))):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.is_contiguous()
+                and x.dtype in dts and x.numel() == n):
+            raise ValueError("%s must be a contiguous device tensor of %d elements of %s"
+                             % (name, n, dts))
+    nbytes = (buf.numel() * buf.element_size()) // 256 * 256
+    code = lib().sh_roof_insert(ctypes.c_void_p(buf.data_ptr()), nbytes,
+                                ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+                                n, ctypes.c_void_p(status.data_ptr()), int(waves_per_cu),
+                                int(depth), ctypes.c_void_p(_stream(stream)))
+    if code != SH_OK:
+        raise SlabHashError("sh_roof_insert", code)

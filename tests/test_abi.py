@@ -132,8 +132,8 @@ def test_roofs_library_exports_and_argument_errors():
         __graft_entry__.build()
     rl = R.lib()
     declared = R.declared_symbols()
-    assert declared == ["sh_roof_run", "sh_roof_search"] and set(declared) == set(R._SIGS)
-    assert hasattr(rl, "sh_roof_run") and hasattr(rl, "sh_roof_search")
+    assert declared == ["sh_roof_insert", "sh_roof_run", "sh_roof_search"]
+    assert set(declared) == set(R._SIGS) and all(hasattr(rl, d) for d in declared)
     buf = ctypes.c_void_p(1 << 20)  # aligned stand-in; every call below fails before using it
     bad = [(7, buf, 1 << 20, 10, 0, 0), (-1, buf, 1 << 20, 10, 0, 0),
            (0, None, 1 << 20, 10, 0, 0), (0, ctypes.c_void_p((1 << 20) + 8), 1 << 20, 10, 0, 0),
@@ -153,6 +153,13 @@ def test_roofs_library_exports_and_argument_errors():
     for p, nbytes, k, n, v, f, wpc, depth in bad:
         assert rl.sh_roof_search(p, nbytes, k, n, v, f, wpc, depth, None) == S.SH_EINVAL
     assert rl.sh_roof_search(buf, 1 << 20, None, 0, None, None, 0, 0, None) == S.SH_OK
+    bad = [(None, 1 << 20, arr, arr, 10, arr, 0, 0), (buf, 300, arr, arr, 10, arr, 0, 0),
+           (buf, 1 << 20, None, arr, 10, arr, 0, 0), (buf, 1 << 20, arr, None, 10, arr, 0, 0),
+           (buf, 1 << 20, arr, arr, 10, None, 0, 0), (buf, 1 << 20, arr, arr, 10, arr, 65, 0),
+           (buf, 1 << 20, arr, arr, 10, arr, 0, 3), (buf, 1 << 20, arr, arr, 1 << 32, arr, 0, 0)]
+    for p, nbytes, k, v, n, st, wpc, depth in bad:
+        assert rl.sh_roof_insert(p, nbytes, k, v, n, st, wpc, depth, None) == S.SH_EINVAL
+    assert rl.sh_roof_insert(buf, 1 << 20, None, None, 0, None, 0, 0, None) == S.SH_OK
 
 
 def test_bench_refuses_more_than_one_gpu():

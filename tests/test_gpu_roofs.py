@@ -1,6 +1,6 @@
 """GPU checks of the access-pattern microbenchmarks: the compare-and-swap patterns write exactly
 where their documented addressing says, the slab-read pattern leaves the buffer unchanged, and the
-one-slab search returns what its documented addressing and vote give."""
+one-slab search and insert return and write what their documented addressing and vote give."""
 import numpy as np
 import pytest
 import torch
@@ -115,4 +115,42 @@ def test_one_slab_search_pattern(depth):
     assert torch.equal(buf, ref)
     assert (found.cpu().numpy() == want_f).all() and int(want_f.sum()) > n // 4
     assert (vals.cpu().numpy().view(np.uint32) == want_v.astype(np.uint32)).all()
+
+
+@pytest.mark.parametrize("depth", [1, 16])
+def test_one_slab_insert_pattern(depth):
+    """Distinct keys into a buffer of all ones: every pair lands in the slab its key's mix
+    selects, slabs fill from slot 0 without gaps, and a status of 1 marks exactly the pairs that
+    landed (an op whose slot another op took, or whose slab is full, loses: the pattern does
+    not retry)."""
+    slabs, n = 257, 9001
+    rng = np.random.default_rng(77 + depth)
+    keys = rng.choice(np.uint64(1) << np.uint64(32), size=n, replace=False).astype(np.uint64)
+    keys = keys[keys != 0xFFFFFFFF]
+    n = keys.size
+    vals = rng.integers(0, 1 << 32, size=n, dtype=np.uint64)
+    buf = torch.full((slabs * 32,), -1, dtype=torch.int64, device="cuda")
+    kd = torch.from_numpy(keys.astype(np.uint32).view(np.int32)).cuda()
+    vd = torch.from_numpy(vals.astype(np.uint32).view(np.int32)).cuda()
+    st = torch.empty(n, dtype=torch.uint8, device="cuda")
+    R.sh_roof_insert(buf, kd, vd, st, 4, depth)
+    torch.cuda.synchronize()
+    got = buf.cpu().numpy().view(np.uint64).reshape(slabs, 32)
+    status = st.cpu().numpy()
+    slab_of = (mix(keys) * slabs) >> 32
+    full = got != np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert not full[:, 31].any()
+    for r in range(slabs):                          # no gaps
+        k = int(full[r, :31].sum())
+        assert full[r, :k].all() and not full[r, k:31].any()
+    stored = got[full]
+    want = (vals << np.uint64(32)) | keys
+    won = status == 1
+    assert set(stored.tolist()) == set(want[won].tolist()) and stored.size == int(won.sum())
+    s_, _ = np.nonzero(full)
+    pos = {int(x): i for i, x in enumerate(want.tolist())}
+    assert all(slab_of[pos[int(x)]] == r for x, r in zip(stored.tolist(), s_.tolist()))
+    per_slab = np.bincount(slab_of.astype(np.int64), minlength=slabs)
+    filled = full[:, :31].sum(1)
+    assert (filled <= np.minimum(per_slab, 31)).all() and ((filled > 0) == (per_slab > 0)).all()
 
