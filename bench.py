@@ -45,14 +45,14 @@ TRAFFIC_SRC_SHA = "f87bfcd2f0d57c57"
 # Per launch, from rocprofv3 TCC_HIT_sum/TCC_MISS_sum and TCC_ATOMIC_sum/TCC_EA0_ATOMIC_sum runs
 # of the same source (profiles/slabhash_step_2p22_l2.md): (L2 hit rate, atomics, atomics that
 # reached memory).
-L2_STATS = {"build": (0.3684, 4693083, 4693083), "search_hit": (0.0937, 0, 0),
-            "search_miss": (0.0937, 0, 0), "mixed": (0.3136, 26729, 26729),
-            "reset": (0.5023, 0, 0)}
+L2_STATS = {"build": (0.3684, 4693064, 4693064), "search_hit": (0.0938, 0, 0),
+            "search_miss": (0.0938, 0, 0), "mixed": (0.3149, 26728, 26728),
+            "reset": (0.5024, 0, 0)}
 # The same for the 2^26-key table of measure_hbm_resident (profiles/slabhash_hbm_2p26_traffic.md).
-HBM_TRAFFIC_BYTES = {"build": 22298785534, "search_hit": 17763170885,
-                     "search_miss": 17763170885}
-TRAFFIC_BYTES = {"build": 1349491597, "search_hit": 1039537699, "search_miss": 1039537699,
-                 "mixed": 19521507, "reset": 56247467}
+HBM_TRAFFIC_BYTES = {"build": 22295350709, "search_hit": 17763213803,
+                     "search_miss": 17763213803}
+TRAFFIC_BYTES = {"build": 1349499276, "search_hit": 1039525491, "search_miss": 1039525491,
+                 "mixed": 19521621, "reset": 56247443}
 
 
 def source_sha() -> str:
